@@ -1,0 +1,145 @@
+/*
+ * psatd.h -- C ABI of the MI355X (gfx950) PSATD Maxwell step with guard cells.
+ *
+ * One call of psatd_step_g1 performs one time step of the ultra-high-order
+ * pseudo-spectral analytical time-domain (PSATD) Maxwell solver on one box of
+ * the global grid (a whole "group" of the hybrid solver, or one sub-domain of
+ * the local solver), as described in Kallala, Vay & Vincenti, "A generalized
+ * massively parallel ultra-high order FFT-based Maxwell solver",
+ * arXiv:1812.07357:
+ *   - guard fill: the box (interior + guard cells) is gathered from the
+ *     global grid G1 (Sec. 2.5.2, coupling step 1; guards of G2 are filled
+ *     from G1, periodic wrap);
+ *   - forward 3D FFT of E, B, J, rho_old, rho_new (Sec. 1.1);
+ *   - analytic k-space push of E and B with order-p modified wavenumbers
+ *     (Sec. 1.1 and 1.3: order p = centred stencil of half width p/2,
+ *     p -> infinity = spectral);
+ *   - inverse 3D FFT of E, B;
+ *   - guard merge: the interior of E, B is copied back to G1 (Sec. 2.5.2,
+ *     coupling step 3).
+ *
+ * Conventions (all entry points):
+ *   - Arrays are contiguous, x fastest: element (i, j, k) of an nx*ny*nz array
+ *     is at offset (k * ny + j) * nx + i.  A torch tensor of shape (nz, ny, nx).
+ *   - Every data pointer is a DEVICE pointer on the current HIP device, of type
+ *     float (PSATD_FP32 plans) or double (PSATD_FP64 plans).  The caller owns
+ *     all field buffers and keeps them alive until the stream has finished.
+ *   - The eleven field slots are, in this order: Ex Ey Ez Bx By Bz Jx Jy Jz
+ *     rho_old rho_new.  J is the current at the half step and is held constant
+ *     over the step; rho_old / rho_new are the charge densities at the start and
+ *     at the end of the step.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = default
+ *     stream) and return without synchronising.  A plan owns its workspace, so
+ *     one plan must not run on two streams at once.
+ *   - Return values: PSATD_OK or a negative PSATD_E* code; psatd_last_error()
+ *     then returns a message for the calling thread.  Errors of kernels already
+ *     in flight surface as PSATD_EHIP at a later call.
+ *   - Units: c and eps0 are plan parameters (1 and 1 by default).
+ */
+#ifndef PSATD_H
+#define PSATD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psatd_plan psatd_plan;
+
+enum {
+  PSATD_OK = 0,
+  PSATD_EINVAL = -1,      /* bad argument (sizes, order, NULL pointer, ...) */
+  PSATD_ENOMEM = -2,      /* device allocation failed; nothing leaked */
+  PSATD_EHIP = -3,        /* HIP runtime error (launch, copy, earlier kernel) */
+  PSATD_EUNSUPPORTED = -4,/* valid request this build cannot serve */
+  PSATD_ESTATE = -5       /* object in the wrong state for the call */
+};
+
+enum { PSATD_FP32 = 0, PSATD_FP64 = 1 };
+
+/* Plan descriptor.  Sizes are INTERIOR cells; the transformed box has
+ * n + 2*ng cells per axis.  order: 0 = infinite order (exact k), otherwise an
+ * even integer >= 2 used on all three axes.  dx, dy, dz > 0; dt != 0; c > 0;
+ * eps0 > 0.  flags must be 0. */
+typedef struct {
+  int nx, ny, nz;
+  int ngx, ngy, ngz;
+  int order;
+  double dx, dy, dz;
+  double dt;
+  double c;
+  double eps0;
+  int precision; /* PSATD_FP32 or PSATD_FP64 */
+  int flags;
+} psatd_plan_desc;
+
+/* Simple constructor of the common case: FP32, c = eps0 = 1, dx = dy = dz,
+ * the same guard width on every side of every axis.  Builds the FFT schedule,
+ * twiddles and PSATD coefficient tables (in FP64 on the device, stored at the
+ * working precision) and allocates the workspace.  Synchronises the device.
+ * Returns NULL on error (psatd_last_error() says why). */
+psatd_plan* psatd_plan_create(int nx, int ny, int nz, int nguard, int order, double dx, double dt);
+
+/* General constructor; *out receives the plan.  Same behaviour as above. */
+int psatd_plan_create_ex(const psatd_plan_desc* desc, psatd_plan** out);
+
+/* Releases a plan.  NULL-safe.  The caller synchronises the plan's stream first. */
+void psatd_plan_destroy(psatd_plan* plan);
+
+/* Box-level step (Sec. 1.1): E and B are advanced in place on box-shaped arrays
+ * of (nx+2ngx) x (ny+2ngy) x (nz+2ngz) cells, the box being taken as periodic.
+ * E[3], B[3]: read and overwritten; J[3], rho_old, rho_new: read only.
+ * All eleven arrays must be distinct. */
+int psatd_push(psatd_plan* plan, void* const E[3], void* const B[3], const void* const J[3],
+               const void* rho_old, const void* rho_new, void* stream);
+
+/* Guard fill (Sec. 2.5.2, step 1): for each of `nfields` arrays,
+ *   box[k][j][i] = g1[(oz-ngz+k) mod GZ][(oy-ngy+j) mod GY][(ox-ngx+i) mod GX]
+ * for the whole box.  g1[f] are global arrays of gdims = {GX, GY, GZ} cells;
+ * box[f] are box-shaped arrays.  origin = {ox, oy, oz} is the global index of
+ * the first interior cell (0 <= o < G).  Guards may be wider than G. */
+int guard_fill(psatd_plan* plan, const void* const* g1, void* const* box, int nfields,
+               const int origin[3], const int gdims[3], void* stream);
+
+/* Guard merge (Sec. 2.5.2, step 3).  mode 0 (copy): the interior of each box
+ * array is written to g1 at (o + i) mod G.  mode 1 (add): every box cell,
+ * guards included, is added to g1 at its wrapped global index (for sources
+ * deposited on boxes); with mode 1 cells that wrap onto the same global cell
+ * are summed in a fixed order, so the result is deterministic. */
+int guard_merge(psatd_plan* plan, const void* const* box, void* const* g1, int nfields,
+                const int origin[3], const int gdims[3], int mode, void* stream);
+
+/* The whole step on G1 with the guard fill fused into the first FFT pass and
+ * the interior merge fused into the last one: g1[0..10] are the eleven global
+ * arrays (gdims cells each); E and B (slots 0..5) are overwritten with the
+ * interior of the advanced box.  Jacobi order: every read of g1 by this call
+ * happens before its first write, so the box may wrap onto itself (a single
+ * group covering the whole periodic grid). */
+int psatd_step_g1(psatd_plan* plan, void* const* g1, const int origin[3], const int gdims[3],
+                  void* stream);
+
+/* Read-only plan properties (for bindings and benchmarks). */
+enum {
+  PSATD_Q_BOX_X = 0, PSATD_Q_BOX_Y = 1, PSATD_Q_BOX_Z = 2,
+  PSATD_Q_PRECISION = 3,
+  PSATD_Q_WORKSPACE_BYTES = 4,  /* device bytes owned by the plan */
+  PSATD_Q_SPECTRUM_POINTS = 5   /* (box_x/2+1) * box_y * box_z */
+};
+int psatd_plan_query(const psatd_plan* plan, int what, long long* value);
+
+/* Copies the plan's PSATD coefficient tables to `dst` (device, plan precision):
+ * 5 consecutive arrays C, S1, X1, X2, X3, each of PSATD_Q_SPECTRUM_POINTS
+ * values, already multiplied by 1/(box_x*box_y*box_z), in the order
+ * [kx][ky][kz] (kz fastest) with kx in [0, box_x/2] and ky, kz over all DFT
+ * indices.  Followed by the three modified-wavenumber tables kx (box_x/2+1
+ * values), ky (box_y), kz (box_z).  dst must hold
+ * 5*PSATD_Q_SPECTRUM_POINTS + box_x/2+1 + box_y + box_z values. */
+int psatd_plan_tables(const psatd_plan* plan, void* dst, void* stream);
+
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char* psatd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSATD_H */

@@ -1,0 +1,537 @@
+// Host runtime of the PSATD library: plans, FFT schedules, workspace, the C ABI.
+//
+// A plan corresponds to one FFT group of the hybrid solver (Sec. 2.6 of
+// arXiv:1812.07357: FFT plans are initialised once per group and the
+// exchange protocol is fixed before the time loop).  It owns the twiddles,
+// the modified-wavenumber and PSATD coefficient tables (built on the device in
+// FP64, Sec. 1.1 / 1.3), the two spectral work arrays and the launch schedule
+// of the five passes.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/psatd.h"
+#include "internal.hpp"
+
+using namespace psatd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int check_hip(const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PSATD_EHIP, "%s: %s", where, hipGetErrorString(e));
+  return PSATD_OK;
+}
+
+constexpr int kThreads = 256;
+constexpr size_t kLdsLimit = 64 * 1024;
+
+inline int lds_stride_h(int n) { return n + ((n & 1) ? 0 : 1); }
+
+// Factor n into compiled radices, largest powers of two first.
+bool make_schedule(int n, int emax, LineSchedule* s) {
+  std::memset(s, 0, sizeof *s);
+  s->n = n;
+  int m = n;
+  std::vector<int> r;
+  const int pow2[] = {16, 8, 4, 2};
+  for (int p : pow2)
+    while (m % p == 0 && p <= emax) {
+      r.push_back(p);
+      m /= p;
+    }
+  while (m % 9 == 0) {
+    r.push_back(9);
+    m /= 9;
+  }
+  const int odd[] = {3, 5, 7, 11, 13, 17};
+  for (int p : odd)
+    while (m % p == 0 && p <= emax) {
+      r.push_back(p);
+      m /= p;
+    }
+  if (m != 1 || (int)r.size() > kMaxStages) return false;
+  if (r.empty()) r.push_back(1);  // n == 1
+  s->nstages = (int)r.size();
+  if (n == 1) s->nstages = 0;
+  for (size_t i = 0; i < r.size() && n > 1; ++i) s->radix[i] = r[i];
+  return true;
+}
+
+// Largest line count per tile (<= cap) that fits the register budget and LDS.
+int fit_lines(const LineSchedule& s, int nth, int emax, size_t csize, int cap) {
+  for (int nl = cap; nl >= 1; --nl) {
+    bool ok = (size_t)nl * lds_stride_h(s.n) * csize <= kLdsLimit;
+    for (int i = 0; i < s.nstages && ok; ++i) {
+      const int R = s.radix[i];
+      const long long bf = (long long)nl * (s.n / R);
+      const long long per = (bf + nth - 1) / nth;
+      if (per > emax / R) ok = false;
+    }
+    if (ok) return nl;
+  }
+  return 0;
+}
+
+template <typename T>
+size_t csz() {
+  return sizeof(cx<T>);
+}
+
+}  // namespace
+
+struct psatd_plan {
+  psatd_plan_desc d{};
+  int NX = 0, NY = 0, NZ = 0, NXH = 0;
+  long long npts = 0, ncell = 0;
+  int fp64 = 0;
+  size_t rsize = 0;  // bytes per real
+  LineSchedule sx{}, sy{}, sz{};
+  int ty = 0;        // real y-lines per P1/P5 tile
+  int nl_y = 0;      // lines per P2/P4 tile
+  int zthreads = 0;  // threads of the P3 block
+  void* twx = nullptr;
+  void* twy = nullptr;
+  void* twz = nullptr;
+  double* kd = nullptr;  // FP64 modified k: kx (NXH), ky (NY), kz (NZ)
+  void* kw = nullptr;    // same at working precision
+  void* coef = nullptr;  // 5 * npts
+  void* wsA = nullptr;   // 11 * npts complex
+  void* wsB = nullptr;   // 11 * npts complex
+  size_t bytes = 0;
+};
+
+namespace {
+
+void free_plan(psatd_plan* p) {
+  if (!p) return;
+  void* ptrs[] = {p->twx, p->twy, p->twz, p->kd, p->kw, p->coef, p->wsA, p->wsB};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+int dalloc(psatd_plan* p, void** out, size_t bytes) {
+  if (hipMalloc(out, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(PSATD_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  p->bytes += bytes;
+  return PSATD_OK;
+}
+
+int validate(const psatd_plan_desc* d) {
+  if (!d) return fail(PSATD_EINVAL, "descriptor is NULL");
+  if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(PSATD_EINVAL, "interior sizes must be positive");
+  if (d->ngx < 0 || d->ngy < 0 || d->ngz < 0) return fail(PSATD_EINVAL, "guard widths must be >= 0");
+  if (d->order < 0 || (d->order % 2) != 0)
+    return fail(PSATD_EINVAL, "order must be 0 (infinite) or an even integer >= 2, got %d", d->order);
+  if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0)) return fail(PSATD_EINVAL, "cell sizes must be > 0");
+  if (!(d->dt == d->dt) || d->dt == 0) return fail(PSATD_EINVAL, "dt must be non-zero");
+  if (!(d->c > 0) || !(d->eps0 > 0)) return fail(PSATD_EINVAL, "c and eps0 must be > 0");
+  if (d->precision != PSATD_FP32 && d->precision != PSATD_FP64) return fail(PSATD_EINVAL, "unknown precision");
+  if (d->flags != 0) return fail(PSATD_EINVAL, "flags must be 0");
+  const long long bx = (long long)d->nx + 2LL * d->ngx, by = (long long)d->ny + 2LL * d->ngy,
+                  bz = (long long)d->nz + 2LL * d->ngz;
+  if (bx > (1 << 20) || by > (1 << 20) || bz > (1 << 20)) return fail(PSATD_EINVAL, "box too large");
+  if ((bx / 2 + 1) * by * bz > (1LL << 40)) return fail(PSATD_EINVAL, "box too large");
+  return PSATD_OK;
+}
+
+int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
+  int rc = validate(d);
+  if (rc) return rc;
+  psatd_plan* p = new psatd_plan;
+  p->d = *d;
+  p->NX = d->nx + 2 * d->ngx;
+  p->NY = d->ny + 2 * d->ngy;
+  p->NZ = d->nz + 2 * d->ngz;
+  p->NXH = p->NX / 2 + 1;
+  p->npts = (long long)p->NXH * p->NY * p->NZ;
+  p->ncell = (long long)p->NX * p->NY * p->NZ;
+  p->fp64 = d->precision == PSATD_FP64;
+  p->rsize = p->fp64 ? 8 : 4;
+  const int em = p->fp64 ? emax<double>::v : emax<float>::v;
+  const size_t cs = 2 * p->rsize;
+  if (!make_schedule(p->NX, em, &p->sx) || !make_schedule(p->NY, em, &p->sy) || !make_schedule(p->NZ, em, &p->sz)) {
+    free_plan(p);
+    return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d has a prime factor above 17 (not supported by this build)",
+                p->NX, p->NY, p->NZ);
+  }
+  const int ncx = fit_lines(p->sx, kThreads, em, cs, 8);
+  p->ty = 2 * ncx;
+  p->nl_y = fit_lines(p->sy, kThreads, em, cs, 16);
+  p->zthreads = 0;
+  for (int nth : {256, 512}) {
+    if (fit_lines(p->sz, nth, em, cs, 11) == 11) {
+      p->zthreads = nth;
+      break;
+    }
+  }
+  if (p->ty == 0 || p->nl_y == 0 || p->zthreads == 0) {
+    free_plan(p);
+    return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d does not fit the LDS / register tiling of this build", p->NX,
+                p->NY, p->NZ);
+  }
+  const size_t npts = (size_t)p->npts;
+  if ((rc = dalloc(p, &p->twx, cs * p->NX)) || (rc = dalloc(p, &p->twy, cs * p->NY)) ||
+      (rc = dalloc(p, &p->twz, cs * p->NZ)) ||
+      (rc = dalloc(p, (void**)&p->kd, 8 * (size_t)(p->NXH + p->NY + p->NZ))) ||
+      (rc = dalloc(p, &p->kw, p->rsize * (size_t)(p->NXH + p->NY + p->NZ))) ||
+      (rc = dalloc(p, &p->coef, 5 * p->rsize * npts)) || (rc = dalloc(p, &p->wsA, 11 * cs * npts)) ||
+      (rc = dalloc(p, &p->wsB, 11 * cs * npts))) {
+    std::string msg = g_err;
+    free_plan(p);
+    return fail(rc, "%s", msg.c_str());
+  }
+  hipStream_t s = nullptr;
+  launch_twiddles(p->twx, p->NX, p->fp64, s);
+  launch_twiddles(p->twy, p->NY, p->fp64, s);
+  launch_twiddles(p->twz, p->NZ, p->fp64, s);
+  launch_modk(p->kd, p->NX, p->NXH, d->dx, d->order, s);
+  launch_modk(p->kd + p->NXH, p->NY, p->NY, d->dy, d->order, s);
+  launch_modk(p->kd + p->NXH + p->NY, p->NZ, p->NZ, d->dz, d->order, s);
+  char* kw = (char*)p->kw;
+  launch_coef(p->coef, kw, kw + p->rsize * p->NXH, kw + p->rsize * (p->NXH + p->NY), p->kd, p->kd + p->NXH,
+              p->kd + p->NXH + p->NY, p->NXH, p->NY, p->NZ, d->dt, d->c, 1.0 / (double)p->ncell, p->fp64, s);
+  if ((rc = check_hip("table kernels")) || hipDeviceSynchronize() != hipSuccess) {
+    if (!rc) rc = check_hip("table build");
+    if (!rc) rc = fail(PSATD_EHIP, "table build failed");
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return PSATD_OK;
+}
+
+// ---------------------------------------------------------------- the five passes
+struct StepIO {
+  const void* src[11];  // P1 sources
+  int gather;
+  int GX, GY, GZ, x0, y0, z0;
+  long long src_extent;
+  void* dst[6];         // P5 destinations
+  int scatter;
+  int ox, oy, oz;
+  long long dst_extent;
+  int y_lo, y_hi, z_lo, z_hi;  // box lines needed after the inverse
+};
+
+template <typename T>
+int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
+  const int NX = p->NX, NY = p->NY, NZ = p->NZ, NXH = p->NXH;
+  const long long npts = p->npts;
+  cx<T>* A = (cx<T>*)p->wsA;
+  cx<T>* B = (cx<T>*)p->wsB;
+  const T* kw = (const T*)p->kw;
+
+  XFwdParams<T> x1{};
+  for (int f = 0; f < 11; ++f) x1.src[f] = (const T*)io.src[f];
+  x1.dst = A;
+  x1.src_extent = io.src_extent;
+  x1.dst_extent = 11 * npts;
+  x1.NX = NX;
+  x1.NY = NY;
+  x1.NZ = NZ;
+  x1.NXH = NXH;
+  x1.ty = p->ty;
+  x1.ytiles = (NY + p->ty - 1) / p->ty;
+  x1.gather = io.gather;
+  x1.GX = io.GX;
+  x1.GY = io.GY;
+  x1.GZ = io.GZ;
+  x1.x0 = io.x0;
+  x1.y0 = io.y0;
+  x1.z0 = io.z0;
+  x1.sch = p->sx;
+  x1.tw = (const cx<T>*)p->twx;
+  launch_xfwd<T>(x1, 11, kThreads, s);
+
+  YPassParams<T> y2{};
+  y2.in = A;
+  y2.out = B;
+  y2.in_extent = 11 * npts;
+  y2.out_extent = 11 * npts;
+  y2.fs_in = npts;
+  y2.os_in = NY;
+  y2.ls_in = (long long)NXH * NY;
+  y2.ps_in = 1;
+  y2.fs_out = npts;
+  y2.os_out = (long long)NY * NZ;
+  y2.ls_out = 1;
+  y2.ps_out = NZ;
+  y2.n = NY;
+  y2.nl = p->nl_y;
+  y2.u_lo = 0;
+  y2.u_hi = NZ;
+  y2.utiles = (NZ + p->nl_y - 1) / p->nl_y;
+  y2.p_lo = 0;
+  y2.p_hi = NY;
+  y2.sch = p->sy;
+  y2.tw = (const cx<T>*)p->twy;
+  launch_ypass<T>(y2, 11, NXH, 0, kThreads, s);
+
+  ZPushParams<T> z3{};
+  z3.b = B;
+  z3.npts = npts;
+  z3.coef = (const T*)p->coef;
+  z3.kx = kw;
+  z3.ky = kw + NXH;
+  z3.kz = kw + NXH + NY;
+  z3.NY = NY;
+  z3.NZ = NZ;
+  z3.NXH = NXH;
+  z3.z_lo = io.z_lo;
+  z3.z_hi = io.z_hi;
+  z3.c2 = T(p->d.c * p->d.c);
+  z3.inv_eps0 = T(1.0 / p->d.eps0);
+  z3.sch = p->sz;
+  z3.tw = (const cx<T>*)p->twz;
+  launch_zpush<T>(z3, p->zthreads, s);
+
+  YPassParams<T> y4{};
+  y4.in = B;
+  y4.out = A;
+  y4.in_extent = 11 * npts;
+  y4.out_extent = 11 * npts;
+  y4.fs_in = npts;
+  y4.os_in = (long long)NY * NZ;
+  y4.ls_in = 1;
+  y4.ps_in = NZ;
+  y4.fs_out = npts;
+  y4.os_out = NY;
+  y4.ls_out = (long long)NXH * NY;
+  y4.ps_out = 1;
+  y4.n = NY;
+  y4.nl = p->nl_y;
+  y4.u_lo = io.z_lo;
+  y4.u_hi = io.z_hi;
+  y4.utiles = (io.z_hi - io.z_lo + p->nl_y - 1) / p->nl_y;
+  y4.p_lo = io.y_lo;
+  y4.p_hi = io.y_hi;
+  y4.sch = p->sy;
+  y4.tw = (const cx<T>*)p->twy;
+  launch_ypass<T>(y4, 6, NXH, 1, kThreads, s);
+
+  XInvParams<T> x5{};
+  x5.src = A;
+  for (int f = 0; f < 6; ++f) x5.dst[f] = (T*)io.dst[f];
+  x5.src_extent = 11 * npts;
+  x5.dst_extent = io.dst_extent;
+  x5.NX = NX;
+  x5.NY = NY;
+  x5.NZ = NZ;
+  x5.NXH = NXH;
+  x5.ty = p->ty;
+  x5.y_lo = io.y_lo;
+  x5.y_hi = io.y_hi;
+  x5.z_lo = io.z_lo;
+  x5.z_hi = io.z_hi;
+  x5.ytiles = (io.y_hi - io.y_lo + p->ty - 1) / p->ty;
+  x5.scatter = io.scatter;
+  x5.GX = io.GX;
+  x5.GY = io.GY;
+  x5.GZ = io.GZ;
+  x5.ox = io.ox;
+  x5.oy = io.oy;
+  x5.oz = io.oz;
+  x5.gx = p->d.ngx;
+  x5.gy = p->d.ngy;
+  x5.gz = p->d.ngz;
+  x5.nx = p->d.nx;
+  x5.sch = p->sx;
+  x5.tw = (const cx<T>*)p->twx;
+  launch_xinv<T>(x5, 6, kThreads, s);
+  return check_hip("step kernels");
+}
+
+int dispatch_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
+  return p->fp64 ? run_step<double>(p, io, s) : run_step<float>(p, io, s);
+}
+
+bool distinct(const void* const* a, int n) {
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j)
+      if (a[i] == a[j]) return false;
+  return true;
+}
+
+int check_geometry(const psatd_plan* p, const int origin[3], const int gdims[3]) {
+  if (!origin || !gdims) return fail(PSATD_EINVAL, "origin / gdims is NULL");
+  const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (gdims[a] <= 0) return fail(PSATD_EINVAL, "global sizes must be positive");
+    if (origin[a] < 0 || origin[a] >= gdims[a]) return fail(PSATD_EINVAL, "origin must lie in [0, gdims)");
+    if (n[a] > gdims[a]) return fail(PSATD_EINVAL, "interior larger than the global grid");
+  }
+  return PSATD_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char* psatd_last_error(void) { return g_err.c_str(); }
+
+int psatd_plan_create_ex(const psatd_plan_desc* desc, psatd_plan** out) {
+  g_err.clear();
+  if (!out) return fail(PSATD_EINVAL, "out is NULL");
+  *out = nullptr;
+  return build_plan(desc, out);
+}
+
+psatd_plan* psatd_plan_create(int nx, int ny, int nz, int nguard, int order, double dx, double dt) {
+  psatd_plan_desc d{};
+  d.nx = nx;
+  d.ny = ny;
+  d.nz = nz;
+  d.ngx = d.ngy = d.ngz = nguard;
+  d.order = order;
+  d.dx = d.dy = d.dz = dx;
+  d.dt = dt;
+  d.c = 1.0;
+  d.eps0 = 1.0;
+  d.precision = PSATD_FP32;
+  d.flags = 0;
+  psatd_plan* p = nullptr;
+  return psatd_plan_create_ex(&d, &p) == PSATD_OK ? p : nullptr;
+}
+
+void psatd_plan_destroy(psatd_plan* plan) { free_plan(plan); }
+
+int psatd_plan_query(const psatd_plan* p, int what, long long* value) {
+  if (!p || !value) return fail(PSATD_EINVAL, "NULL argument");
+  switch (what) {
+    case PSATD_Q_BOX_X: *value = p->NX; break;
+    case PSATD_Q_BOX_Y: *value = p->NY; break;
+    case PSATD_Q_BOX_Z: *value = p->NZ; break;
+    case PSATD_Q_PRECISION: *value = p->d.precision; break;
+    case PSATD_Q_WORKSPACE_BYTES: *value = (long long)p->bytes; break;
+    case PSATD_Q_SPECTRUM_POINTS: *value = p->npts; break;
+    default: return fail(PSATD_EINVAL, "unknown query %d", what);
+  }
+  return PSATD_OK;
+}
+
+int psatd_plan_tables(const psatd_plan* p, void* dst, void* stream) {
+  if (!p || !dst) return fail(PSATD_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nc = 5 * (size_t)p->npts * p->rsize;
+  const size_t nk = (size_t)(p->NXH + p->NY + p->NZ) * p->rsize;
+  if (hipMemcpyAsync(dst, p->coef, nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync((char*)dst + nc, p->kw, nk, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return check_hip("psatd_plan_tables");
+  return PSATD_OK;
+}
+
+int psatd_push(psatd_plan* p, void* const E[3], void* const B[3], const void* const J[3], const void* rho_old,
+               const void* rho_new, void* stream) {
+  if (!p || !E || !B || !J) return fail(PSATD_EINVAL, "NULL argument");
+  StepIO io{};
+  const void* all[11] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2], rho_old, rho_new};
+  for (int f = 0; f < 11; ++f) {
+    if (!all[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
+    io.src[f] = all[f];
+  }
+  if (!distinct(all, 11)) return fail(PSATD_EINVAL, "field arrays must be distinct");
+  for (int f = 0; f < 3; ++f) {
+    io.dst[f] = E[f];
+    io.dst[3 + f] = B[f];
+  }
+  io.gather = 0;
+  io.src_extent = p->ncell;
+  io.scatter = 0;
+  io.dst_extent = p->ncell;
+  io.y_lo = 0;
+  io.y_hi = p->NY;
+  io.z_lo = 0;
+  io.z_hi = p->NZ;
+  return dispatch_step(p, io, (hipStream_t)stream);
+}
+
+int psatd_step_g1(psatd_plan* p, void* const* g1, const int origin[3], const int gdims[3], void* stream) {
+  if (!p || !g1) return fail(PSATD_EINVAL, "NULL argument");
+  int rc = check_geometry(p, origin, gdims);
+  if (rc) return rc;
+  for (int f = 0; f < 11; ++f)
+    if (!g1[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
+  if (!distinct(g1, 11)) return fail(PSATD_EINVAL, "field arrays must be distinct");
+  StepIO io{};
+  for (int f = 0; f < 11; ++f) io.src[f] = g1[f];
+  for (int f = 0; f < 6; ++f) io.dst[f] = g1[f];
+  io.gather = 1;
+  io.scatter = 1;
+  io.GX = gdims[0];
+  io.GY = gdims[1];
+  io.GZ = gdims[2];
+  const int g[3] = {p->d.ngx, p->d.ngy, p->d.ngz};
+  int st[3];
+  for (int a = 0; a < 3; ++a) st[a] = (int)((((long long)origin[a] - g[a]) % gdims[a] + gdims[a]) % gdims[a]);
+  io.x0 = st[0];
+  io.y0 = st[1];
+  io.z0 = st[2];
+  io.ox = origin[0];
+  io.oy = origin[1];
+  io.oz = origin[2];
+  io.src_extent = (long long)gdims[0] * gdims[1] * gdims[2];
+  io.dst_extent = io.src_extent;
+  io.y_lo = p->d.ngy;
+  io.y_hi = p->d.ngy + p->d.ny;
+  io.z_lo = p->d.ngz;
+  io.z_hi = p->d.ngz + p->d.nz;
+  return dispatch_step(p, io, (hipStream_t)stream);
+}
+
+int guard_fill(psatd_plan* p, const void* const* g1, void* const* box, int nfields, const int origin[3],
+               const int gdims[3], void* stream) {
+  if (!p || !g1 || !box) return fail(PSATD_EINVAL, "NULL argument");
+  if (nfields < 1 || nfields > 16) return fail(PSATD_EINVAL, "nfields must be in [1, 16]");
+  int rc = check_geometry(p, origin, gdims);
+  if (rc) return rc;
+  for (int f = 0; f < nfields; ++f)
+    if (!g1[f] || !box[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
+  const int bd[3] = {p->NX, p->NY, p->NZ};
+  const int g[3] = {p->d.ngx, p->d.ngy, p->d.ngz};
+  int st[3];
+  for (int a = 0; a < 3; ++a) st[a] = (int)((((long long)origin[a] - g[a]) % gdims[a] + gdims[a]) % gdims[a]);
+  launch_guard_fill(g1, box, nfields, (int)p->rsize, bd, st, gdims, (hipStream_t)stream);
+  return check_hip("guard_fill");
+}
+
+int guard_merge(psatd_plan* p, const void* const* box, void* const* g1, int nfields, const int origin[3],
+                const int gdims[3], int mode, void* stream) {
+  if (!p || !g1 || !box) return fail(PSATD_EINVAL, "NULL argument");
+  if (nfields < 1 || nfields > 16) return fail(PSATD_EINVAL, "nfields must be in [1, 16]");
+  if (mode != 0 && mode != 1) return fail(PSATD_EINVAL, "mode must be 0 (copy) or 1 (add)");
+  int rc = check_geometry(p, origin, gdims);
+  if (rc) return rc;
+  for (int f = 0; f < nfields; ++f)
+    if (!g1[f] || !box[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
+  const int bd[3] = {p->NX, p->NY, p->NZ};
+  const int g[3] = {p->d.ngx, p->d.ngy, p->d.ngz};
+  const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
+  launch_guard_merge(box, g1, nfields, (int)p->rsize, bd, g, n, origin, gdims, mode, (hipStream_t)stream);
+  return check_hip("guard_merge");
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Plan-time tables, computed on the device in FP64 and stored at working precision.
+//
+// * FFT twiddles w_n^m = exp(-2 pi i m / n).
+// * Order-p modified wavenumbers (Sec. 1.1 and 1.3 of arXiv:1812.07357: a
+//   solver of order p uses a centred stencil of half width p/2; p = infinity is
+//   the spectral derivative).  For the centred order-p first derivative on a
+//   collocated grid the symbol is
+//       k_p = sum_{l=1..m} b_l 2 sin(l k d) / d,  m = p / 2,
+//   with b_1 = m / (m + 1) and b_{l+1} = -b_l l (m - l) / ((l + 1)(m + l + 1)).
+//   The sine argument l k d = 2 pi l |m'| / n is reduced exactly in integers.
+//   k_p is odd in k and zero at the Nyquist index (it is zero there for every
+//   finite p, and kept zero at infinite order so that real fields stay real).
+// * PSATD coefficients per half-spectrum point, omega = c |K|, theta = omega dt:
+//       C = cos theta, S1 = sin theta / omega, X1 = (1 - C) / omega^2,
+//       X2 = (1 - S1/dt) / omega^2, X3 = (C - S1/dt) / omega^2,
+//   from their Taylor series in theta^2 below theta = 0.1 (the direct forms
+//   cancel catastrophically there), all multiplied by 1/(NX NY NZ) so that the
+//   inverse transforms can stay unnormalised.
+
+#include "internal.hpp"
+
+namespace psatd {
+
+namespace {
+
+constexpr int kT = 256;
+
+template <typename T>
+__global__ void k_twiddles(cx<T>* dst, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double s, c;
+  sincospi(-2.0 * (double)m / (double)n, &s, &c);
+  dst[m] = {T(c), T(s)};
+}
+
+__global__ void k_modk(double* dst, int n, int count, double d, int order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const long long ms = (2LL * i <= n) ? i : (long long)i - n;
+  if (2LL * i == n) {  // Nyquist
+    dst[i] = 0.0;
+    return;
+  }
+  const long long am = ms < 0 ? -ms : ms;
+  double kp;
+  if (order == 0) {
+    kp = 2.0 * (double)am / ((double)n * d) * 3.14159265358979323846;
+  } else {
+    const int m = order / 2;
+    double b = (double)m / (double)(m + 1);
+    double acc = 0.0;
+    for (int l = 1; l <= m; ++l) {
+      // sin(2 pi l am / n) with the argument reduced modulo n exactly
+      const long long num = (2LL * l * am) % (2LL * n);
+      acc += b * 2.0 * sinpi((double)num / (double)n);
+      b = -b * (double)l * (double)(m - l) / ((double)(l + 1) * (double)(m + l + 1));
+    }
+    kp = acc / d;
+  }
+  dst[i] = ms < 0 ? -kp : kp;
+}
+
+template <typename T>
+__global__ void k_convert(const double* src, T* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = T(src[i]);
+}
+
+template <typename T>
+__global__ void k_coef(T* coef, const double* kx, const double* ky, const double* kz, int NXH, int NY, int NZ,
+                       double dt, double c, double norm) {
+  const long long npts = (long long)NXH * NY * NZ;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= npts) return;
+  const int iz = (int)(q % NZ);
+  const long long r = q / NZ;
+  const int iy = (int)(r % NY);
+  const int ix = (int)(r / NY);
+  const double k2 = kx[ix] * kx[ix] + ky[iy] * ky[iy] + kz[iz] * kz[iz];
+  const double om = c * sqrt(k2);
+  const double th = om * dt;
+  const double t2 = th * th;
+  const double C = cos(th);
+  double S1, X1, X2, X3;
+  if (fabs(th) < 0.1) {
+    const double dt2 = dt * dt;
+    S1 = dt * (1.0 + t2 * (-1.0 / 6 + t2 * (1.0 / 120 + t2 * (-1.0 / 5040 + t2 * (1.0 / 362880)))));
+    X1 = dt2 * (0.5 + t2 * (-1.0 / 24 + t2 * (1.0 / 720 + t2 * (-1.0 / 40320 + t2 * (1.0 / 3628800)))));
+    X2 = dt2 * (1.0 / 6 + t2 * (-1.0 / 120 + t2 * (1.0 / 5040 + t2 * (-1.0 / 362880 + t2 * (1.0 / 39916800)))));
+    X3 = dt2 * (-1.0 / 3 + t2 * (1.0 / 30 + t2 * (-1.0 / 840 + t2 * (1.0 / 45360 + t2 * (-1.0 / 3991680)))));
+  } else {
+    const double om2 = om * om;
+    S1 = sin(th) / om;
+    X1 = (1.0 - C) / om2;
+    X2 = (1.0 - S1 / dt) / om2;
+    X3 = (C - S1 / dt) / om2;
+  }
+  coef[q] = T(C * norm);
+  coef[npts + q] = T(S1 * norm);
+  coef[2 * npts + q] = T(X1 * norm);
+  coef[3 * npts + q] = T(X2 * norm);
+  coef[4 * npts + q] = T(X3 * norm);
+}
+
+inline unsigned nblk(long long n) { return (unsigned)((n + kT - 1) / kT); }
+
+}  // namespace
+
+void launch_twiddles(void* dst, int n, int fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_twiddles<double>, dim3(nblk(n)), dim3(kT), 0, s, (cx<double>*)dst, n);
+  else
+    hipLaunchKernelGGL(k_twiddles<float>, dim3(nblk(n)), dim3(kT), 0, s, (cx<float>*)dst, n);
+}
+
+void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s) {
+  hipLaunchKernelGGL(k_modk, dim3(nblk(count)), dim3(kT), 0, s, dst, n, count, d, order);
+}
+
+void launch_coef(void* coef, void* kxw, void* kyw, void* kzw, const double* kx, const double* ky,
+                 const double* kz, int NXH, int NY, int NZ, double dt, double c, double norm, int fp64,
+                 hipStream_t s) {
+  const long long npts = (long long)NXH * NY * NZ;
+  if (fp64) {
+    hipLaunchKernelGGL(k_coef<double>, dim3(nblk(npts)), dim3(kT), 0, s, (double*)coef, kx, ky, kz, NXH, NY, NZ,
+                       dt, c, norm);
+    hipLaunchKernelGGL(k_convert<double>, dim3(nblk(NXH)), dim3(kT), 0, s, kx, (double*)kxw, NXH);
+    hipLaunchKernelGGL(k_convert<double>, dim3(nblk(NY)), dim3(kT), 0, s, ky, (double*)kyw, NY);
+    hipLaunchKernelGGL(k_convert<double>, dim3(nblk(NZ)), dim3(kT), 0, s, kz, (double*)kzw, NZ);
+  } else {
+    hipLaunchKernelGGL(k_coef<float>, dim3(nblk(npts)), dim3(kT), 0, s, (float*)coef, kx, ky, kz, NXH, NY, NZ,
+                       dt, c, norm);
+    hipLaunchKernelGGL(k_convert<float>, dim3(nblk(NXH)), dim3(kT), 0, s, kx, (float*)kxw, NXH);
+    hipLaunchKernelGGL(k_convert<float>, dim3(nblk(NY)), dim3(kT), 0, s, ky, (float*)kyw, NY);
+    hipLaunchKernelGGL(k_convert<float>, dim3(nblk(NZ)), dim3(kT), 0, s, kz, (float*)kzw, NZ);
+  }
+}
+
+}  // namespace psatd

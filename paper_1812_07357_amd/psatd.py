@@ -1,0 +1,239 @@
+"""ctypes binding of libpsatd.so (the C ABI in include/psatd.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.  If the
+library has not been built, importing this module raises -- there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpsatd.so")
+
+PSATD_OK = 0
+PSATD_EINVAL = -1
+PSATD_ENOMEM = -2
+PSATD_EHIP = -3
+PSATD_EUNSUPPORTED = -4
+PSATD_ESTATE = -5
+PSATD_FP32 = 0
+PSATD_FP64 = 1
+
+Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS = range(6)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("ngx", ctypes.c_int), ("ngy", ctypes.c_int), ("ngz", ctypes.c_int),
+        ("order", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("dt", ctypes.c_double), ("c", ctypes.c_double), ("eps0", ctypes.c_double),
+        ("precision", ctypes.c_int), ("flags", ctypes.c_int),
+    ]
+
+
+class PsatdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"psatd error {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """dlopen libpsatd.so and declare the C signatures (no GPU needed)."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1812_07357_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    vp, ip, cint = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int
+    vpp = ctypes.POINTER(ctypes.c_void_p)
+    lib.psatd_plan_create.restype = vp
+    lib.psatd_plan_create.argtypes = [cint, cint, cint, cint, cint, ctypes.c_double, ctypes.c_double]
+    lib.psatd_plan_create_ex.restype = cint
+    lib.psatd_plan_create_ex.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    lib.psatd_plan_destroy.restype = None
+    lib.psatd_plan_destroy.argtypes = [vp]
+    lib.psatd_push.restype = cint
+    lib.psatd_push.argtypes = [vp, vpp, vpp, vpp, vp, vp, vp]
+    lib.guard_fill.restype = cint
+    lib.guard_fill.argtypes = [vp, vpp, vpp, cint, ip, ip, vp]
+    lib.guard_merge.restype = cint
+    lib.guard_merge.argtypes = [vp, vpp, vpp, cint, ip, ip, cint, vp]
+    lib.psatd_step_g1.restype = cint
+    lib.psatd_step_g1.argtypes = [vp, vpp, ip, ip, vp]
+    lib.psatd_plan_query.restype = cint
+    lib.psatd_plan_query.argtypes = [vp, cint, ctypes.POINTER(ctypes.c_longlong)]
+    lib.psatd_plan_tables.restype = cint
+    lib.psatd_plan_tables.argtypes = [vp, vp, vp]
+    lib.psatd_last_error.restype = ctypes.c_char_p
+    lib.psatd_last_error.argtypes = []
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(rc: int):
+    if rc != PSATD_OK:
+        raise PsatdError(rc, _lib.psatd_last_error().decode())
+
+
+def _ptrs(tensors) -> ctypes.Array:
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _ints(v) -> ctypes.Array:
+    return (ctypes.c_int * 3)(*[int(x) for x in v])
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _triple(v):
+    return (v, v, v) if isinstance(v, (int, float)) else tuple(v)
+
+
+class Plan:
+    """One PSATD plan: a guard-padded box of the global grid (one FFT group).
+
+    Sizes are interior cells (x, y, z); ``nguard`` a scalar or per-axis
+    triple; ``order`` 0 for infinite order, else even >= 2; ``dx`` scalar or
+    triple; ``precision`` "fp32" or "fp64".
+    """
+
+    def __init__(self, nx, ny, nz, nguard=0, order=0, dx=1.0, dt=0.5, c=1.0, eps0=1.0, precision="fp32"):
+        import torch
+
+        g = _triple(nguard)
+        d = _triple(dx)
+        desc = PlanDesc(int(nx), int(ny), int(nz), int(g[0]), int(g[1]), int(g[2]), int(order),
+                        float(d[0]), float(d[1]), float(d[2]), float(dt), float(c), float(eps0),
+                        PSATD_FP64 if precision == "fp64" else PSATD_FP32, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.psatd_plan_create_ex(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        self.interior = (int(nx), int(ny), int(nz))
+        self.nguard = tuple(int(v) for v in g)
+        self.order = int(order)
+        self.dx = tuple(float(v) for v in d)
+        self.dt = float(dt)
+        self.c = float(c)
+        self.eps0 = float(eps0)
+        self.precision = "fp64" if precision == "fp64" else "fp32"
+        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
+        self.box = (self.query(Q_BOX_X), self.query(Q_BOX_Y), self.query(Q_BOX_Z))
+
+    # -- properties -------------------------------------------------------------
+    @property
+    def box_shape(self):
+        """Torch shape (NZ, NY, NX) of a box array."""
+        return (self.box[2], self.box[1], self.box[0])
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_longlong()
+        _check(_lib.psatd_plan_query(self._h, what, ctypes.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.psatd_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- checks -------------------------------------------------------------------
+    def _check_fields(self, tensors, shape, name):
+        for t in tensors:
+            if not t.is_cuda:
+                raise ValueError(f"{name}: tensors must be on the GPU")
+            if t.dtype != self.dtype:
+                raise ValueError(f"{name}: dtype {t.dtype} does not match the plan ({self.dtype})")
+            if not t.is_contiguous():
+                raise ValueError(f"{name}: tensors must be contiguous")
+            if tuple(t.shape) != tuple(shape):
+                raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+
+    @staticmethod
+    def _split(fields, n):
+        if hasattr(fields, "dim") and fields.dim() == 4:
+            if fields.shape[0] != n:
+                raise ValueError(f"expected {n} fields, got {fields.shape[0]}")
+            return [fields[i] for i in range(n)]
+        if len(fields) != n:
+            raise ValueError(f"expected {n} fields, got {len(fields)}")
+        return list(fields)
+
+    # -- entry points -----------------------------------------------------------------
+    def push(self, E: Sequence, B: Sequence, J: Sequence, rho_old, rho_new, stream=None):
+        """psatd_push: advance box arrays E, B (3 each, in place) by one step."""
+        allf = list(E) + list(B) + list(J) + [rho_old, rho_new]
+        self._check_fields(allf, self.box_shape, "push")
+        _check(_lib.psatd_push(self._h, _ptrs(E), _ptrs(B), _ptrs(J), ctypes.c_void_p(rho_old.data_ptr()),
+                               ctypes.c_void_p(rho_new.data_ptr()), _stream(stream)))
+
+    def push_fields(self, fields, stream=None):
+        """push() on an (11, NZ, NY, NX) tensor (or a list of 11) in slot order."""
+        f = self._split(fields, 11)
+        self.push(f[0:3], f[3:6], f[6:9], f[9], f[10], stream)
+
+    def step_g1(self, g1, origin, stream=None):
+        """psatd_step_g1: fused fill + step + merge on the 11 global arrays (E, B updated in place)."""
+        f = self._split(g1, 11)
+        gshape = tuple(f[0].shape)
+        self._check_fields(f, gshape, "step_g1")
+        gdims = (gshape[2], gshape[1], gshape[0])
+        _check(_lib.psatd_step_g1(self._h, _ptrs(f), _ints(origin), _ints(gdims), _stream(stream)))
+
+    def guard_fill(self, g1, box, origin, stream=None):
+        """guard_fill: gather box arrays (interior + guards) from the periodic global arrays."""
+        g = list(g1)
+        b = list(box)
+        if len(g) != len(b) or not g:
+            raise ValueError("guard_fill: g1 and box must hold the same number of arrays")
+        gshape = tuple(g[0].shape)
+        self._check_fields(g, gshape, "guard_fill g1")
+        self._check_fields(b, self.box_shape, "guard_fill box")
+        gdims = (gshape[2], gshape[1], gshape[0])
+        _check(_lib.guard_fill(self._h, _ptrs(g), _ptrs(b), len(g), _ints(origin), _ints(gdims), _stream(stream)))
+
+    def guard_merge(self, box, g1, origin, mode=0, stream=None):
+        """guard_merge: copy (mode 0) or add (mode 1) box arrays back into the global arrays."""
+        g = list(g1)
+        b = list(box)
+        if len(g) != len(b) or not g:
+            raise ValueError("guard_merge: g1 and box must hold the same number of arrays")
+        gshape = tuple(g[0].shape)
+        self._check_fields(g, gshape, "guard_merge g1")
+        self._check_fields(b, self.box_shape, "guard_merge box")
+        gdims = (gshape[2], gshape[1], gshape[0])
+        _check(_lib.guard_merge(self._h, _ptrs(b), _ptrs(g), len(g), _ints(origin), _ints(gdims), int(mode),
+                                _stream(stream)))
+
+    def tables(self, stream=None):
+        """Coefficient tables (5, NXH, NY, NZ) and 1D modified k (kx, ky, kz) at working precision."""
+        import torch
+
+        npts = self.query(Q_SPECTRUM_POINTS)
+        NX, NY, NZ = self.box
+        nxh = NX // 2 + 1
+        buf = torch.empty(5 * npts + nxh + NY + NZ, dtype=self.dtype, device="cuda")
+        _check(_lib.psatd_plan_tables(self._h, ctypes.c_void_p(buf.data_ptr()), _stream(stream)))
+        coef = buf[: 5 * npts].view(5, nxh, NY, NZ)
+        k = buf[5 * npts:]
+        return coef, k[:nxh], k[nxh:nxh + NY], k[nxh + NY:]
