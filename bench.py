@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of one PSATD step (guard fill + FFT + k-space push + inverse FFT + merge) on one MI355X.
+
+Workload: one group of the hybrid solver on one GPU -- a 512 x 256 x 256 cell
+periodic grid G1 with 32 guard cells per side and axis (box 576 x 320 x 320),
+order p = 100 modified wavenumbers, dt = dx / (2c), FP32.  Inputs are seeded
+and synthetic: a Gaussian laser pulse (wavelength 16 dx, waist 40 dx, length
+3 wavelengths) plus N(0, 0.01) noise on E and B, J and rho from 1e6
+random-walk macro-particles deposited with cloud-in-cell weights.
+
+One step = one psatd_step_g1 call on inputs already resident in HBM.  The same
+workload is also timed in FP64.  Prints ONE JSON line (rank 0, N = 1).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell-updates/s per PSATD step (FP32 vs FP64) + % HBM roofline, 1 MI355X"
+INTERIOR = (512, 256, 256)  # x, y, z
+NGUARD = 32
+ORDER = 100
+DX = 1.0
+DT = 0.5
+PASSES = ("x_fwd_fill", "y_fwd", "z_push", "y_inv", "x_inv_merge")
+KERNELS = {"x_fwd_fill": "k_xfwd", "y_fwd": "k_ypass<-1>", "z_push": "k_zpush", "y_inv": "k_ypass<1>",
+           "x_inv_merge": "k_xinv"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(interior, d, dt, seed_stream=0):
+    """(11, NZ, NY, NX) float64 host array of the seeded laser + noise + macro-particle workload."""
+    import synth
+
+    nx, ny, nz = interior
+    shape = (nz, ny, nx)
+    rng = synth.rng_for(2, seed_stream)
+    lam = 16.0 * d
+    out = np.empty((11,) + shape)
+    E, B = synth.laser_pulse(shape, d, wavelength=lam, waist=40.0 * d, length=3 * lam, x_center=0.5 * nx * d)
+    out[0:3] = E
+    out[3:6] = B
+    del E, B
+    for i in range(6):
+        out[i] += rng.normal(0.0, 0.01, size=shape)
+    J, rho_old, rho_new = synth.macro_particle_deposit(rng, shape, d, dt, 1_000_000, q=0.1)
+    out[6:9] = J
+    out[9] = rho_old
+    out[10] = rho_new
+    return out
+
+
+def algorithmic_bytes(box, interior, ng, s):
+    """Bytes each pass must move per launch (reads + writes), s = bytes per real.
+
+    Units: NX*NY*NZ box cells, npts = (NX/2+1)*NY*NZ half-spectrum points.
+    x_fwd_fill reads 11 real fields over the box and writes 11 half spectra;
+    y_fwd reads and writes 11 half spectra; z_push reads 11 half spectra and the
+    5 coefficient tables and writes 6 half spectra for the interior z range;
+    y_inv reads those and writes the interior (y, z) lines; x_inv_merge reads
+    them and writes the interior cells of 6 fields.
+    """
+    NX, NY, NZ = box
+    nx, ny, nz = interior
+    nxh = NX // 2 + 1
+    c = 2 * s
+    npts = nxh * NY * NZ
+    return {
+        "x_fwd_fill": 11 * NX * NY * NZ * s + 11 * npts * c,
+        "y_fwd": 2 * 11 * npts * c,
+        "z_push": 11 * npts * c + 5 * npts * s + 6 * nxh * NY * nz * c,
+        "y_inv": 6 * nxh * NY * nz * c + 6 * nxh * ny * nz * c,
+        "x_inv_merge": 6 * nxh * ny * nz * c + 6 * nx * ny * nz * s,
+    }
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for name in ("passes.hip", "fft_lds.hpp", "cplx.hpp", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1812_07357_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_pass, digest):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_config2_fp32.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_digest") != digest:
+        return None
+    entry = rec.get("passes", {}).get(kernel_pass)
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def run_gpu(precision, inputs_host, steps, warmup):
+    import torch
+
+    from paper_1812_07357_amd import psatd
+
+    nx, ny, nz = INTERIOR
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    plan = psatd.Plan(nx, ny, nz, nguard=NGUARD, order=ORDER, dx=DX, dt=DT, precision=precision)
+    g1 = torch.as_tensor(inputs_host, dtype=dtype).to("cuda")
+    origin = (0, 0, 0)
+    for _ in range(warmup):
+        plan.step_g1(g1, origin)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.pass_times()  # discard anything recorded so far
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.step_g1(g1, origin)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    passes, nrec = plan.pass_times()
+    plan.set_timing(False)
+    ms = (t1 - t0) * 1e3 / steps
+    res = {"ms_per_step": ms, "passes_ms": passes, "recorded_steps": nrec, "box": plan.box,
+           "workspace_bytes": plan.query(psatd.Q_WORKSPACE_BYTES)}
+    fields = g1[0:6].clone()
+    plan.close()
+    del g1
+    torch.cuda.empty_cache()
+    return res, fields
+
+
+def cpu_baseline():
+    """The FP64 oracle on a half-scale copy of the workload: one local step of a
+    256 x 128 x 128 grid with 16 guards (box 288 x 160 x 160, same box/interior ratio)."""
+    import oracle.step
+    from oracle import domain
+
+    interior = (256, 128, 128)
+    g1 = make_inputs(interior, DX, DT, seed_stream=7)
+    box = {"origin": (0, 0, 0), "interior": interior, "nguard": 16, "order": ORDER}
+    t0 = time.perf_counter()
+    domain.local_step(g1, [box], DX, DT)
+    t = time.perf_counter() - t0
+    cells = interior[0] * interior[1] * interior[2]
+    return {"value": cells / t, "unit": "cell-updates/s", "cores": oracle.step.WORKERS, "kind": "oracle",
+            "sample": f"1 FP64 step of the oracle (complex FFTs, order 100) on a 256x128x128 grid + 16 guards "
+                      f"(box 288x160x160, same box/interior ratio as the workload), {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the PSATD step of one group runs on a single MI355X "
+              "(multi-GPU groups are not part of this build); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    log("generating inputs")
+    host = make_inputs(INTERIOR, DX, DT)
+    nx, ny, nz = INTERIOR
+    interior_cells = nx * ny * nz
+
+    log("fp32 run")
+    r32, f32 = run_gpu("fp32", host, args.steps, args.warmup)
+    box = r32["box"]
+    box_cells = box[0] * box[1] * box[2]
+    value = interior_cells / (r32["ms_per_step"] * 1e-3)
+
+    digest = source_digest()
+    alg = algorithmic_bytes(box, INTERIOR, NGUARD, 4)
+    dom = max(PASSES, key=lambda k: r32["passes_ms"][k])
+    dom_ms = r32["passes_ms"][dom]
+    achieved = alg[dom] / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom, digest),
+                "kernel": KERNELS[dom], "pass": dom, "kernel_ms": round(dom_ms, 4),
+                "algorithmic_bytes_per_launch": alg[dom]}
+    step_alg = sum(alg.values())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "PSATD step of one group: 512x256x256 interior + 32 guards per side "
+                               "(box 576x320x320), order 100, dt=dx/2c, FP32, fused guard fill/merge",
+                   "interior": list(INTERIOR), "nguard": NGUARD, "order": ORDER, "box": list(box), "dt": DT},
+        "roofline": roofline,
+        "box_cell_updates_per_s": box_cells / (r32["ms_per_step"] * 1e-3),
+        "passes_ms_fp32": {k: round(v, 4) for k, v in r32["passes_ms"].items()},
+        "step_algorithmic_hbm_frac_fp32": round(step_alg / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "source_digest": digest,
+    }
+
+    if not args.no_fp64:
+        log("fp64 run")
+        r64, f64 = run_gpu("fp64", host, args.steps, args.warmup)
+        alg64 = algorithmic_bytes(box, INTERIOR, NGUARD, 8)
+        out["fp64"] = {
+            "value": interior_cells / (r64["ms_per_step"] * 1e-3),
+            "ms_per_step": r64["ms_per_step"],
+            "passes_ms": {k: round(v, 4) for k, v in r64["passes_ms"].items()},
+            "step_algorithmic_hbm_frac": round(sum(alg64.values()) / (r64["ms_per_step"] * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS, 4),
+        }
+        out["fp32_speedup_over_fp64"] = r64["ms_per_step"] / r32["ms_per_step"]
+        # FP32 vs FP64 error after warmup + steps steps of the same input, per vector field
+        e = (f32.double() - f64)
+        out["fp32_vs_fp64_rel_l2"] = {
+            "steps": args.warmup + args.steps,
+            "E": float(e[0:3].norm() / f64[0:3].norm()),
+            "B": float(e[3:6].norm() / f64[3:6].norm()),
+        }
+        del f64, e
+    del f32
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

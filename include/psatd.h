@@ -135,6 +135,16 @@ int psatd_plan_query(const psatd_plan* plan, int what, long long* value);
  * 5*PSATD_Q_SPECTRUM_POINTS + box_x/2+1 + box_y + box_z values. */
 int psatd_plan_tables(const psatd_plan* plan, void* dst, void* stream);
 
+/* Per-pass timing for benchmarks.  While enabled, every step records HIP
+ * events on its stream before and after each of its five passes (x forward
+ * with guard fill, y forward, z forward + push + z inverse, y inverse, x
+ * inverse with guard merge).  psatd_plan_pass_times waits for the last
+ * recorded step, returns the mean duration of each pass in milliseconds over
+ * the steps recorded since timing was enabled (or since the previous call),
+ * their number in *nsteps, and releases the events. */
+int psatd_plan_set_timing(psatd_plan* plan, int enable);
+int psatd_plan_pass_times(psatd_plan* plan, double ms[5], long long* nsteps);
+
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char* psatd_last_error(void);
 

@@ -44,6 +44,51 @@ PSATD_HD __forceinline__ cx<T> mul_si(cx<T> a) {
   else return {-a.im, a.re};
 }
 
+// x * c for a compile-time constant c.  In FP32 the constant is carried as an
+// unevaluated sum hi + lo of two floats, so that the product is as accurate as
+// with an exact constant: a transform applied every time step with rounded
+// constants would repeat the same rounding error each step and let it add up
+// coherently, while rounding of the data itself varies from step to step.
+PSATD_HD __forceinline__ float mulc(float x, double c) {
+  const float hi = (float)c;
+  const float lo = (float)(c - (double)hi);
+  return fmaf(x, hi, x * lo);
+}
+PSATD_HD __forceinline__ double mulc(double x, double c) { return x * c; }
+// a + x * c
+PSATD_HD __forceinline__ float fmac(float x, double c, float a) {
+  const float hi = (float)c;
+  const float lo = (float)(c - (double)hi);
+  return fmaf(x, hi, fmaf(x, lo, a));
+}
+PSATD_HD __forceinline__ double fmac(double x, double c, double a) { return fma(x, c, a); }
+
+// Run-time twiddle w = exp(-2 pi i m / n): FP32 tables hold w as hi + lo pairs.
+template <typename T>
+struct Tw;
+template <>
+struct Tw<float> {
+  cx<float> hi, lo;
+};
+template <>
+struct Tw<double> {
+  cx<double> hi;
+};
+// v * w (S < 0, forward) or v * conj(w) (S > 0, inverse)
+template <int S>
+PSATD_HD __forceinline__ cx<float> twmul(cx<float> v, const Tw<float>& w) {
+  const float hr = w.hi.re, lr = w.lo.re;
+  const float hi = (S < 0) ? w.hi.im : -w.hi.im;
+  const float li = (S < 0) ? w.lo.im : -w.lo.im;
+  const float cr = v.re * lr - v.im * li;
+  const float ci = v.re * li + v.im * lr;
+  return {fmaf(v.re, hr, fmaf(-v.im, hi, cr)), fmaf(v.re, hi, fmaf(v.im, hr, ci))};
+}
+template <int S>
+PSATD_HD __forceinline__ cx<double> twmul(cx<double> v, const Tw<double>& w) {
+  return (S < 0) ? cmul(v, w.hi) : cmulc(v, w.hi);
+}
+
 // ------------------------------------------------------------------ constexpr trig
 namespace ce {
 constexpr double kPi = 3.14159265358979323846264338327950288;
@@ -112,13 +157,13 @@ PSATD_HD __forceinline__ cx<T> twiddle_const(cx<T> x) {
   } else if constexpr (4 * e == 3 * N) {
     return mul_si<-S>(x);
   } else if constexpr (8 * e == N || 8 * e == 3 * N || 8 * e == 5 * N || 8 * e == 7 * N) {
-    constexpr T h = T(0.70710678118654752440084436210484904);
+    constexpr double h = 0.70710678118654752440084436210484904;
     constexpr double c = tw_const<S, e, N>::c, s = tw_const<S, e, N>::s;
     constexpr T sc = T(c > 0 ? 1 : -1), ss = T(s > 0 ? 1 : -1);
-    return {h * (sc * x.re - ss * x.im), h * (sc * x.im + ss * x.re)};
+    return {mulc(sc * x.re - ss * x.im, h), mulc(sc * x.im + ss * x.re, h)};
   } else {
-    constexpr T c = T(tw_const<S, e, N>::c), s = T(tw_const<S, e, N>::s);
-    return {c * x.re - s * x.im, c * x.im + s * x.re};
+    constexpr double c = tw_const<S, e, N>::c, s = tw_const<S, e, N>::s;
+    return {fmac(x.re, c, mulc(-x.im, s)), fmac(x.im, c, mulc(x.re, s))};
   }
 }
 
@@ -143,12 +188,12 @@ template <int R, int U, int TT, typename T>
 struct odd_acc {
   static PSATD_HD __forceinline__ void run(cx<T>& a, cx<T>& b, const cx<T>* sp, const cx<T>* sm) {
     if constexpr (TT <= (R - 1) / 2) {
-      constexpr T c = T(tw_const<1, U * TT, R>::c);
-      constexpr T s = T(tw_const<1, U * TT, R>::s);
-      a.re += c * sp[TT].re;
-      a.im += c * sp[TT].im;
-      b.re += s * sm[TT].re;
-      b.im += s * sm[TT].im;
+      constexpr double c = tw_const<1, U * TT, R>::c;
+      constexpr double s = tw_const<1, U * TT, R>::s;
+      a.re = fmac(sp[TT].re, c, a.re);
+      a.im = fmac(sp[TT].im, c, a.im);
+      b.re = fmac(sm[TT].re, s, b.re);
+      b.im = fmac(sm[TT].im, s, b.im);
       odd_acc<R, U, TT + 1, T>::run(a, b, sp, sm);
     }
   }

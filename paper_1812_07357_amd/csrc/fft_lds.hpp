@@ -37,7 +37,7 @@ struct emax<double> { static constexpr int v = 17; };
 
 template <int R, int S, typename T>
 __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, int n, int Ns,
-                                               const cx<T>* __restrict__ tw) {
+                                               const Tw<T>* __restrict__ tw) {
   constexpr int MB = emax<T>::v / R;
   static_assert(MB >= 1, "radix larger than the register budget");
   const int bfl = n / R;
@@ -61,8 +61,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, i
       if (k != 0) {
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          const cx<T> w = tw[k * t * twstep];
-          v[b][t] = (S < 0) ? cmul(v[b][t], w) : cmulc(v[b][t], w);
+          v[b][t] = twmul<S>(v[b][t], tw[k * t * twstep]);
         }
       }
       dft<R, S, T>::run(v[b]);
@@ -85,7 +84,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, i
 // Must be called by every thread of the block (it synchronises).
 template <int S, typename T>
 __device__ __forceinline__ void lds_fft(cx<T>* lds, int ld, int nlines, const LineSchedule& sch,
-                                        const cx<T>* __restrict__ tw) {
+                                        const Tw<T>* __restrict__ tw) {
   int Ns = 1;
   const int n = sch.n;
   for (int s = 0; s < sch.nstages; ++s) {

@@ -32,7 +32,7 @@ struct XFwdParams {
   int GX, GY, GZ;
   int x0, y0, z0;        // (origin - nguard) mod G, non-negative
   LineSchedule sch;
-  const cx<T>* tw;
+  const Tw<T>* tw;
 };
 
 // P2 / P4: transform along the middle index of a tile of lines and transpose.
@@ -50,7 +50,7 @@ struct YPassParams {
   int utiles;            // tiles along u
   int p_lo, p_hi;        // output positions written: [p_lo, p_hi)
   LineSchedule sch;
-  const cx<T>* tw;
+  const Tw<T>* tw;
 };
 
 // P3: z-axis forward transform of 11 fields, k-space push, inverse z transform of E, B.
@@ -67,7 +67,7 @@ struct ZPushParams {
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
   LineSchedule sch;
-  const cx<T>* tw;
+  const Tw<T>* tw;
 };
 
 // P5: x-axis complex-to-real inverse of pairs of y-lines from layout A, to box
@@ -89,7 +89,7 @@ struct XInvParams {
   int gx, gy, gz;        // guard widths
   int nx;                // interior cells along x
   LineSchedule sch;
-  const cx<T>* tw;
+  const Tw<T>* tw;
 };
 
 template <typename T>

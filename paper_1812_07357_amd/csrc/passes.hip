@@ -313,6 +313,14 @@ void launch_ypass(const YPassParams<T>& p, int nfields, int nouter, int inverse,
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
   const size_t lds = (size_t)11 * lds_stride(p.NZ) * cx_bytes<T>();
+  if (lds > 64 * 1024) {
+    // Opt in to more than 64 KB of dynamic LDS (the plan checked the device limit).
+    static size_t granted = 0;
+    if (lds > granted &&
+        hipFuncSetAttribute((const void*)k_zpush<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+            hipSuccess)
+      granted = lds;
+  }
   dim3 grid((unsigned)((i64)p.NXH * p.NY));
   hipLaunchKernelGGL(k_zpush<T>, grid, dim3(nthreads), lds, s, p);
 }

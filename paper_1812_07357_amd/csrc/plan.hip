@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -42,7 +43,18 @@ int check_hip(const char* where) {
 }
 
 constexpr int kThreads = 256;
-constexpr size_t kLdsLimit = 64 * 1024;
+
+// LDS a single workgroup may use on the current device (160 KB per workgroup on
+// gfx950; 64 KB if the query fails).
+size_t lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return (size_t)v;
+}
 
 inline int lds_stride_h(int n) { return n + ((n & 1) ? 0 : 1); }
 
@@ -76,10 +88,10 @@ bool make_schedule(int n, int emax, LineSchedule* s) {
   return true;
 }
 
-// Largest line count per tile (<= cap) that fits the register budget and LDS.
-int fit_lines(const LineSchedule& s, int nth, int emax, size_t csize, int cap) {
+// Largest line count per tile (<= cap) that fits the register budget and `lds` bytes.
+int fit_lines(const LineSchedule& s, int nth, int emax, size_t csize, int cap, size_t lds) {
   for (int nl = cap; nl >= 1; --nl) {
-    bool ok = (size_t)nl * lds_stride_h(s.n) * csize <= kLdsLimit;
+    bool ok = (size_t)nl * lds_stride_h(s.n) * csize <= lds;
     for (int i = 0; i < s.nstages && ok; ++i) {
       const int R = s.radix[i];
       const long long bf = (long long)nl * (s.n / R);
@@ -117,12 +129,22 @@ struct psatd_plan {
   void* wsA = nullptr;   // 11 * npts complex
   void* wsB = nullptr;   // 11 * npts complex
   size_t bytes = 0;
+  int timing = 0;
+  std::vector<std::array<hipEvent_t, 6>> events;  // per recorded step
 };
 
 namespace {
 
+void release_events(psatd_plan* p) {
+  for (auto& set : p->events)
+    for (hipEvent_t e : set)
+      if (e) (void)hipEventDestroy(e);
+  p->events.clear();
+}
+
 void free_plan(psatd_plan* p) {
   if (!p) return;
+  release_events(p);
   void* ptrs[] = {p->twx, p->twy, p->twz, p->kd, p->kw, p->coef, p->wsA, p->wsB};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -177,12 +199,15 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
     return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d has a prime factor above 17 (not supported by this build)",
                 p->NX, p->NY, p->NZ);
   }
-  const int ncx = fit_lines(p->sx, kThreads, em, cs, 8);
+  // Tiles of the x and y passes stay within 64 KB (several workgroups per CU);
+  // the z pass must hold all 11 lines of a column and may use the device limit.
+  const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
+  const int ncx = fit_lines(p->sx, kThreads, em, cs, 8, lds_small);
   p->ty = 2 * ncx;
-  p->nl_y = fit_lines(p->sy, kThreads, em, cs, 16);
+  p->nl_y = fit_lines(p->sy, kThreads, em, cs, 16, lds_small);
   p->zthreads = 0;
   for (int nth : {256, 512}) {
-    if (fit_lines(p->sz, nth, em, cs, 11) == 11) {
+    if (fit_lines(p->sz, nth, em, cs, 11, lds_limit()) == 11) {
       p->zthreads = nth;
       break;
     }
@@ -193,8 +218,9 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
                 p->NY, p->NZ);
   }
   const size_t npts = (size_t)p->npts;
-  if ((rc = dalloc(p, &p->twx, cs * p->NX)) || (rc = dalloc(p, &p->twy, cs * p->NY)) ||
-      (rc = dalloc(p, &p->twz, cs * p->NZ)) ||
+  const size_t tws = p->fp64 ? sizeof(Tw<double>) : sizeof(Tw<float>);
+  if ((rc = dalloc(p, &p->twx, tws * p->NX)) || (rc = dalloc(p, &p->twy, tws * p->NY)) ||
+      (rc = dalloc(p, &p->twz, tws * p->NZ)) ||
       (rc = dalloc(p, (void**)&p->kd, 8 * (size_t)(p->NXH + p->NY + p->NZ))) ||
       (rc = dalloc(p, &p->kw, p->rsize * (size_t)(p->NXH + p->NY + p->NZ))) ||
       (rc = dalloc(p, &p->coef, 5 * p->rsize * npts)) || (rc = dalloc(p, &p->wsA, 11 * cs * npts)) ||
@@ -236,9 +262,28 @@ struct StepIO {
   int y_lo, y_hi, z_lo, z_hi;  // box lines needed after the inverse
 };
 
+// Records event `i` of the current step when timing is on.
+struct Marks {
+  std::array<hipEvent_t, 6>* set = nullptr;
+  hipStream_t s = nullptr;
+  void mark(int i) {
+    if (set) (void)hipEventRecord((*set)[i], s);
+  }
+};
+
 template <typename T>
 int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   const int NX = p->NX, NY = p->NY, NZ = p->NZ, NXH = p->NXH;
+  Marks mk;
+  mk.s = s;
+  if (p->timing) {
+    std::array<hipEvent_t, 6> set{};
+    for (auto& e : set)
+      if (hipEventCreate(&e) != hipSuccess) return check_hip("hipEventCreate");
+    p->events.push_back(set);
+    mk.set = &p->events.back();
+  }
+  mk.mark(0);
   const long long npts = p->npts;
   cx<T>* A = (cx<T>*)p->wsA;
   cx<T>* B = (cx<T>*)p->wsB;
@@ -263,8 +308,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x1.y0 = io.y0;
   x1.z0 = io.z0;
   x1.sch = p->sx;
-  x1.tw = (const cx<T>*)p->twx;
+  x1.tw = (const Tw<T>*)p->twx;
   launch_xfwd<T>(x1, 11, kThreads, s);
+  mk.mark(1);
 
   YPassParams<T> y2{};
   y2.in = A;
@@ -287,8 +333,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   y2.p_lo = 0;
   y2.p_hi = NY;
   y2.sch = p->sy;
-  y2.tw = (const cx<T>*)p->twy;
+  y2.tw = (const Tw<T>*)p->twy;
   launch_ypass<T>(y2, 11, NXH, 0, kThreads, s);
+  mk.mark(2);
 
   ZPushParams<T> z3{};
   z3.b = B;
@@ -305,8 +352,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   z3.c2 = T(p->d.c * p->d.c);
   z3.inv_eps0 = T(1.0 / p->d.eps0);
   z3.sch = p->sz;
-  z3.tw = (const cx<T>*)p->twz;
+  z3.tw = (const Tw<T>*)p->twz;
   launch_zpush<T>(z3, p->zthreads, s);
+  mk.mark(3);
 
   YPassParams<T> y4{};
   y4.in = B;
@@ -329,8 +377,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   y4.p_lo = io.y_lo;
   y4.p_hi = io.y_hi;
   y4.sch = p->sy;
-  y4.tw = (const cx<T>*)p->twy;
+  y4.tw = (const Tw<T>*)p->twy;
   launch_ypass<T>(y4, 6, NXH, 1, kThreads, s);
+  mk.mark(4);
 
   XInvParams<T> x5{};
   x5.src = A;
@@ -359,8 +408,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x5.gz = p->d.ngz;
   x5.nx = p->d.nx;
   x5.sch = p->sx;
-  x5.tw = (const cx<T>*)p->twx;
+  x5.tw = (const Tw<T>*)p->twx;
   launch_xinv<T>(x5, 6, kThreads, s);
+  mk.mark(5);
   return check_hip("step kernels");
 }
 
@@ -442,6 +492,31 @@ int psatd_plan_tables(const psatd_plan* p, void* dst, void* stream) {
       hipMemcpyAsync((char*)dst + nc, p->kw, nk, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return check_hip("psatd_plan_tables");
   return PSATD_OK;
+}
+
+int psatd_plan_set_timing(psatd_plan* p, int enable) {
+  if (!p) return fail(PSATD_EINVAL, "NULL plan");
+  p->timing = enable ? 1 : 0;
+  return PSATD_OK;
+}
+
+int psatd_plan_pass_times(psatd_plan* p, double ms[5], long long* nsteps) {
+  if (!p || !ms || !nsteps) return fail(PSATD_EINVAL, "NULL argument");
+  for (int i = 0; i < 5; ++i) ms[i] = 0.0;
+  *nsteps = (long long)p->events.size();
+  if (p->events.empty()) return PSATD_OK;
+  if (hipEventSynchronize(p->events.back()[5]) != hipSuccess) {
+    release_events(p);
+    return check_hip("hipEventSynchronize");
+  }
+  for (auto& set : p->events)
+    for (int i = 0; i < 5; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, set[i], set[i + 1]) == hipSuccess) ms[i] += t;
+    }
+  for (int i = 0; i < 5; ++i) ms[i] /= (double)p->events.size();
+  release_events(p);
+  return check_hip("psatd_plan_pass_times");
 }
 
 int psatd_push(psatd_plan* p, void* const E[3], void* const B[3], const void* const J[3], const void* rho_old,

@@ -1,6 +1,6 @@
 // Plan-time tables, computed on the device in FP64 and stored at working precision.
 //
-// * FFT twiddles w_n^m = exp(-2 pi i m / n).
+// * FFT twiddles w_n^m = exp(-2 pi i m / n) (FP32: as hi + lo pairs of floats).
 // * Order-p modified wavenumbers (Sec. 1.1 and 1.3 of arXiv:1812.07357: a
 //   solver of order p uses a centred stencil of half width p/2; p = infinity is
 //   the spectral derivative).  For the centred order-p first derivative on a
@@ -25,13 +25,21 @@ namespace {
 
 constexpr int kT = 256;
 
-template <typename T>
-__global__ void k_twiddles(cx<T>* dst, int n) {
+// FP32 twiddles are stored as hi + lo float pairs (hi = rounded value, lo = rounded remainder).
+__global__ void k_twiddles_f32(Tw<float>* dst, int n) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   double s, c;
   sincospi(-2.0 * (double)m / (double)n, &s, &c);
-  dst[m] = {T(c), T(s)};
+  const float ch = (float)c, sh = (float)s;
+  dst[m] = {{ch, sh}, {(float)(c - (double)ch), (float)(s - (double)sh)}};
+}
+__global__ void k_twiddles_f64(Tw<double>* dst, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double s, c;
+  sincospi(-2.0 * (double)m / (double)n, &s, &c);
+  dst[m] = {{c, s}};
 }
 
 __global__ void k_modk(double* dst, int n, int count, double d, int order) {
@@ -109,9 +117,9 @@ inline unsigned nblk(long long n) { return (unsigned)((n + kT - 1) / kT); }
 
 void launch_twiddles(void* dst, int n, int fp64, hipStream_t s) {
   if (fp64)
-    hipLaunchKernelGGL(k_twiddles<double>, dim3(nblk(n)), dim3(kT), 0, s, (cx<double>*)dst, n);
+    hipLaunchKernelGGL(k_twiddles_f64, dim3(nblk(n)), dim3(kT), 0, s, (Tw<double>*)dst, n);
   else
-    hipLaunchKernelGGL(k_twiddles<float>, dim3(nblk(n)), dim3(kT), 0, s, (cx<float>*)dst, n);
+    hipLaunchKernelGGL(k_twiddles_f32, dim3(nblk(n)), dim3(kT), 0, s, (Tw<float>*)dst, n);
 }
 
 void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s) {

@@ -69,6 +69,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_plan_query.argtypes = [vp, cint, ctypes.POINTER(ctypes.c_longlong)]
     lib.psatd_plan_tables.restype = cint
     lib.psatd_plan_tables.argtypes = [vp, vp, vp]
+    lib.psatd_plan_set_timing.restype = cint
+    lib.psatd_plan_set_timing.argtypes = [vp, cint]
+    lib.psatd_plan_pass_times.restype = cint
+    lib.psatd_plan_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     lib.psatd_last_error.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     return lib
@@ -224,6 +228,19 @@ class Plan:
         gdims = (gshape[2], gshape[1], gshape[0])
         _check(_lib.guard_merge(self._h, _ptrs(b), _ptrs(g), len(g), _ints(origin), _ints(gdims), int(mode),
                                 _stream(stream)))
+
+    PASS_NAMES = ("x_fwd_fill", "y_fwd", "z_push", "y_inv", "x_inv_merge")
+
+    def set_timing(self, enable: bool):
+        """Record HIP events around each pass of every following step."""
+        _check(_lib.psatd_plan_set_timing(self._h, 1 if enable else 0))
+
+    def pass_times(self):
+        """Mean milliseconds per pass since timing was enabled (waits for the last step)."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_longlong()
+        _check(_lib.psatd_plan_pass_times(self._h, ms, ctypes.byref(n)))
+        return dict(zip(self.PASS_NAMES, list(ms))), int(n.value)
 
     def tables(self, stream=None):
         """Coefficient tables (5, NXH, NY, NZ) and 1D modified k (kx, ky, kz) at working precision."""

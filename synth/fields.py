@@ -133,9 +133,9 @@ def laser_pulse(shape, d, wavelength: float, waist: float, length: float, x_cent
 def _cic(shape, pos, weight):
     """Cloud-in-cell deposit of ``weight`` at positions ``pos`` (n, 3) in cell units, periodic."""
     nz, ny, nx = shape
-    out = np.zeros(nx * ny * nz)
     i0 = np.floor(pos).astype(np.int64)
     f = pos - i0
+    idx, wts = [], []
     for cx in (0, 1):
         wx = f[:, 0] if cx else 1.0 - f[:, 0]
         ix = (i0[:, 0] + cx) % nx
@@ -145,8 +145,9 @@ def _cic(shape, pos, weight):
             for cz in (0, 1):
                 wz = f[:, 2] if cz else 1.0 - f[:, 2]
                 iz = (i0[:, 2] + cz) % nz
-                flat = (iz * ny + iy) * nx + ix
-                out += np.bincount(flat, weights=weight * wx * wy * wz, minlength=out.size)
+                idx.append((iz * ny + iy) * nx + ix)
+                wts.append(weight * wx * wy * wz)
+    out = np.bincount(np.concatenate(idx), weights=np.concatenate(wts), minlength=nx * ny * nz)
     return out.reshape(shape)
 
 

@@ -1,0 +1,135 @@
+"""Full-size parity in the benchmark's launch configuration, checked point by point.
+
+A full FP64 CPU transform of a 576 x 320 x 320 (or 1056 x 544 x 544) box takes
+minutes, so these tests use inputs whose exact output the oracle can evaluate
+at any point in O(number of modes): sums of Fourier modes that are periodic on
+both the global grid G1 and the guard-padded box.  For such inputs the local
+solve with guards is exact (no truncation error at the box edges), every mode
+is advanced on its own by the analytic push (Sec. 1.1 of arXiv:1812.07357), and
+the oracle's few-mode evaluator gives the expected fields at sampled interior
+cells.  The GPU runs exactly the plan and entry point that bench.py times.
+
+Tolerances: FP64 1e-11 relative (max norm over samples); FP32 2e-6 relative
+L2 / 2e-5 max norm after one step; FP32 after 100 steps <= 1e-5 relative L2 per
+vector field (E and B separately), the target error of the FP32 path.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import modes
+
+pytestmark = pytest.mark.gpu
+
+
+def _draw_modes(rng, period, nmodes):
+    """Distinct integer mode vectors j (physical k = 2 pi j / (period d)), |j_a| < period / 2."""
+    lim = period // 2 - 1
+    seen, out = set(), []
+    while len(out) < nmodes:
+        m = tuple(int(v) for v in rng.integers(-lim, lim + 1, size=3))
+        if m == (0, 0, 0) or m in seen or tuple(-v for v in m) in seen:
+            continue
+        seen.add(m)
+        out.append(m)
+    return np.array(out)
+
+
+def _synthesize_gpu(kvec, coefs, gshape, d):
+    """Mode sums on the global grid, evaluated on the GPU in FP64 (test input construction)."""
+    import torch
+
+    nz, ny, nx = gshape
+    x = torch.arange(nx, dtype=torch.float64, device="cuda") * d
+    y = torch.arange(ny, dtype=torch.float64, device="cuda") * d
+    z = torch.arange(nz, dtype=torch.float64, device="cuda") * d
+    out = torch.zeros((coefs.shape[0],) + tuple(gshape), dtype=torch.float64, device="cuda")
+    for j in range(kvec.shape[0]):
+        ex = torch.exp(1j * kvec[j, 0] * x)
+        ey = torch.exp(1j * kvec[j, 1] * y)
+        ez = torch.exp(1j * kvec[j, 2] * z)
+        plane = ez[:, None, None] * ey[None, :, None] * ex[None, None, :]
+        for f in range(coefs.shape[0]):
+            out[f] += 2.0 * (complex(coefs[f, j]) * plane).real
+        del plane
+    return out
+
+
+def _sample_points(rng, gshape, n):
+    nz, ny, nx = gshape
+    k = rng.integers(0, nz, size=n)
+    j = rng.integers(0, ny, size=n)
+    i = rng.integers(0, nx, size=n)
+    # add two full x-lines so that every x tile and the wrap seams are covered
+    k = np.concatenate([k, np.full(nx, nz // 3), np.full(nx, nz - 1)])
+    j = np.concatenate([j, np.full(nx, ny // 2), np.full(nx, 0)])
+    i = np.concatenate([i, np.arange(nx), np.arange(nx)])
+    return k, j, i
+
+
+def _run_case(lib, interior, ng, order, period, precisions, steps_list, seed, nmodes=10, nsamples=20000):
+    import torch
+
+    d, dt = 1.0, 0.5
+    nx, ny, nz = interior
+    gshape = (nz, ny, nx)
+    rng = np.random.default_rng(seed)
+    m = _draw_modes(rng, period, nmodes)
+    kvec = 2 * np.pi * m / (period * d)
+    coefs = rng.standard_normal((11, nmodes)) + 1j * rng.standard_normal((11, nmodes))
+    g64 = _synthesize_gpu(kvec, coefs, gshape, d)
+    k, j, i = _sample_points(rng, gshape, nsamples)
+    pos = np.stack([i * d, j * d, k * d], axis=1)
+    kt, jt, it = (torch.as_tensor(a, device="cuda") for a in (k, j, i))
+    results = {}
+    for precision in precisions:
+        plan = lib.Plan(nx, ny, nz, nguard=ng, order=order, dx=d, dt=dt, precision=precision)
+        g = g64.to(plan.dtype, copy=True).contiguous()
+        done = 0
+        for nsteps in steps_list:
+            while done < nsteps:
+                plan.step_g1(g, (0, 0, 0))
+                done += 1
+            torch.cuda.synchronize()
+            got = g[0:6][:, kt, jt, it].double().cpu().numpy()
+            exact = modes.synthesize(kvec, modes.push_modes(kvec, coefs, d, dt, order, nsteps=nsteps), pos)
+            results[(precision, nsteps)] = (got, exact)
+            print(f"  {precision} {interior} ng={ng} p={order} after {nsteps} steps: "
+                  f"E {np.linalg.norm(got[0:3] - exact[0:3]) / np.linalg.norm(exact[0:3]):.2e} "
+                  f"B {np.linalg.norm(got[3:6] - exact[3:6]) / np.linalg.norm(exact[3:6]):.2e}", flush=True)
+        plan.close()
+        del g
+    del g64
+    torch.cuda.empty_cache()
+    return results
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_benchmark_workload_fp32_and_fp64(lib):
+    """512x256x256 + 32 guards (box 576x320x320), p = 100: modes of period 64 cells."""
+    res = _run_case(lib, (512, 256, 256), 32, 100, 64, ("fp64", "fp32"), (1, 100), seed=2)
+    got, exact = res[("fp64", 1)]
+    assert _rel_max(got, exact) <= 1e-11
+    got, exact = res[("fp32", 1)]
+    assert _rel_l2(got, exact) <= 2e-6 and _rel_max(got, exact) <= 2e-5
+    got, exact = res[("fp32", 100)]
+    assert _rel_l2(got[0:3], exact[0:3]) <= 1e-5
+    assert _rel_l2(got[3:6], exact[3:6]) <= 1e-5
+    got, exact = res[("fp64", 100)]
+    assert _rel_max(got, exact) <= 1e-10
+
+
+def test_precision_study_box_fp32_and_fp64(lib):
+    """1024x512x512 + 16 guards (box 1056x544x544 = 2^5 3 11 x 2^5 17), p = 32: period 32 cells."""
+    res = _run_case(lib, (1024, 512, 512), 16, 32, 32, ("fp64", "fp32"), (1,), seed=4, nmodes=6)
+    got, exact = res[("fp64", 1)]
+    assert _rel_max(got, exact) <= 1e-11
+    got, exact = res[("fp32", 1)]
+    assert _rel_l2(got, exact) <= 2e-6 and _rel_max(got, exact) <= 2e-5
