@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PSATD step of one group runs on a single MI355X "
@@ -183,6 +185,16 @@ def main():
     host = make_inputs(INTERIOR, DX, DT)
     nx, ny, nz = INTERIOR
     interior_cells = nx * ny * nz
+
+    if args.calibration_copy:
+        # A plain 1 GiB device-to-device copy: under a counter profiler its
+        # FETCH_SIZE / WRITE_SIZE calibrate the counters against known bytes.
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy of 1 GiB done")
 
     log("fp32 run")
     r32, f32 = run_gpu("fp32", host, args.steps, args.warmup)

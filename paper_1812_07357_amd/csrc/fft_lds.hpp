@@ -10,70 +10,97 @@
 // which leaves the transform in natural order after the last stage.  The
 // stage runs in place: every thread first reads all of its butterflies into
 // registers, the block synchronises, then every thread writes.
+//
+// Element i of a line lives at LDS slot i + i/16 of that line: the first stage
+// writes with a stride of R elements, and without the padding slot every
+// lane of a 16-lane group would hit the same LDS bank for R = 16.
 #pragma once
 
 #include "cplx.hpp"
+
+#include <cstdint>
 
 namespace psatd {
 
 constexpr int kMaxStages = 16;
 
+// Division by a run-time constant d via a multiply-high: q = (mulhi(x, m) + x) >> s,
+// exact for 0 <= x < 2^31 (s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0, 0};
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+  return f;
+}
+__device__ __forceinline__ int fdiv(int x, const FastDiv& f) {
+  return (int)((__umulhi((uint32_t)x, f.m) + (uint32_t)x) >> f.s);
+}
+
 struct LineSchedule {
   int n;
   int nstages;
   int radix[kMaxStages];
+  FastDiv bfl[kMaxStages];  // n / radix[s]
+  FastDiv ns[kMaxStages];   // product of radix[0..s-1]
 };
-
-// Radices with a compiled stage; anything else must be factored by the host.
-// (Keep in sync with the switch in lds_fft.)
-inline constexpr int kRadices[] = {16, 13, 11, 9, 8, 7, 5, 4, 3, 2, 17};
 
 template <typename T>
 struct emax;  // register budget: complex values a thread holds through one stage
 template <>
-struct emax<float> { static constexpr int v = 32; };
+struct emax<float> { static constexpr int v = 17; };
 template <>
 struct emax<double> { static constexpr int v = 17; };
 
+__host__ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// LDS slots per line of n elements (odd, so that lanes walking across lines use distinct banks).
+__host__ __device__ __forceinline__ int lds_line(int n) { return (lpad(n - 1) + 1) | 1; }
+
 template <int R, int S, typename T>
-__device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, int n, int Ns,
-                                               const Tw<T>* __restrict__ tw) {
+__device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, int n, int Ns, const FastDiv& fb,
+                                               const FastDiv& fn, const Tw<T>* __restrict__ tw) {
   constexpr int MB = emax<T>::v / R;
   static_assert(MB >= 1, "radix larger than the register budget");
-  const int bfl = n / R;
+  const int bfl = (int)fb.d;
   const int total = nlines * bfl;
   const int nth = blockDim.x;
   const int tid = threadIdx.x;
   const int twstep = n / (Ns * R);
   cx<T> v[MB][R];
-  int obase[MB];
+  int lbase[MB];  // LDS offset of the butterfly's line, -1 if none
+  int obase[MB];  // first output position (jj - k) R + k within the line
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
     const int j = tid + b * nth;
-    obase[b] = -1;
+    lbase[b] = -1;
+    obase[b] = 0;
     if (j < total) {
-      const int line = j / bfl;
+      const int line = fdiv(j, fb);
       const int jj = j - line * bfl;
-      const int k = jj % Ns;
-      const cx<T>* src = lds + line * ld + jj;
+      const int k = jj - fdiv(jj, fn) * Ns;
+      const cx<T>* src = lds + line * ld;
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = src[t * bfl];
+      for (int t = 0; t < R; ++t) v[b][t] = src[lpad(jj + t * bfl)];
       if (k != 0) {
 #pragma unroll
-        for (int t = 1; t < R; ++t) {
-          v[b][t] = twmul<S>(v[b][t], tw[k * t * twstep]);
-        }
+        for (int t = 1; t < R; ++t) v[b][t] = twmul<S>(v[b][t], tw[k * t * twstep]);
       }
       dft<R, S, T>::run(v[b]);
-      obase[b] = line * ld + (jj - k) * R + k;
+      lbase[b] = line * ld;
+      obase[b] = (jj - k) * R + k;
     }
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
-    if (obase[b] >= 0) {
+    if (lbase[b] >= 0) {
+      cx<T>* dst = lds + lbase[b];
 #pragma unroll
-      for (int t = 0; t < R; ++t) lds[obase[b] + t * Ns] = v[b][t];
+      for (int t = 0; t < R; ++t) dst[lpad(obase[b] + t * Ns)] = v[b][t];
     }
   }
   __syncthreads();
@@ -89,18 +116,20 @@ __device__ __forceinline__ void lds_fft(cx<T>* lds, int ld, int nlines, const Li
   const int n = sch.n;
   for (int s = 0; s < sch.nstages; ++s) {
     const int R = sch.radix[s];
+    const FastDiv& fb = sch.bfl[s];
+    const FastDiv& fn = sch.ns[s];
     switch (R) {
-      case 2: stockham_stage<2, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 3: stockham_stage<3, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 4: stockham_stage<4, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 5: stockham_stage<5, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 7: stockham_stage<7, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 8: stockham_stage<8, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 9: stockham_stage<9, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 11: stockham_stage<11, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 13: stockham_stage<13, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 16: stockham_stage<16, S, T>(lds, ld, nlines, n, Ns, tw); break;
-      case 17: stockham_stage<17, S, T>(lds, ld, nlines, n, Ns, tw); break;
+      case 2: stockham_stage<2, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 3: stockham_stage<3, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 4: stockham_stage<4, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 5: stockham_stage<5, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 7: stockham_stage<7, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 8: stockham_stage<8, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 9: stockham_stage<9, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 11: stockham_stage<11, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 13: stockham_stage<13, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 16: stockham_stage<16, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 17: stockham_stage<17, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
       default: break;  // the host never schedules another radix
     }
     Ns *= R;

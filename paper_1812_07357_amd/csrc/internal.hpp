@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "fft_lds.hpp"
+#include "gmem.hpp"
 
 namespace psatd {
 
@@ -17,38 +18,50 @@ using i64 = long long;
 // Every pass reads whole contiguous lines on one side and writes tiles of
 // consecutive lines (a short contiguous run per position) on the other.
 
+// Every pass runs as a persistent kernel: a grid sized to the resident capacity
+// walks over the pass's tiles, and while one tile is transformed in LDS the
+// loads of the block's next tile are already in flight.  Arrays are addressed
+// through buffer resources (see gmem.hpp), one resource per field.
+
 // P1: x-axis real-to-complex transform of pairs of y-lines (two real lines form
 // one complex line), box arrays or a periodic gather from G1, into layout A.
 template <typename T>
 struct XFwdParams {
   const T* src[11];
-  cx<T>* dst;            // layout A, nfields * NZ * NXH * NY
-  i64 src_extent;        // elements in each source array
-  i64 dst_extent;        // elements in dst
+  uint32_t src_bytes;    // bytes of each source array
+  cx<T>* dst;            // layout A; field f starts at dst + f * npts
+  i64 npts;
+  uint32_t dst_bytes;    // bytes of one field of A
   int NX, NY, NZ, NXH;
   int ty;                // real y-lines per tile (even)
-  int ytiles;
+  int ytiles, ntiles;    // tiles per (field, z) and in total
   int gather;            // 0: src is box shaped; 1: src is G1 (GX, GY, GZ) with wrap
   int GX, GY, GZ;
   int x0, y0, z0;        // (origin - nguard) mod G, non-negative
+  FastDiv fd_ytiles, fd_NZ, fd_NX, fd_GX, fd_GY, fd_GZ, fd_ty;
+  int ld_drow, ld_dcol;  // block stride over (complex line, x) = divmod(threads, NX)
+  int wr_drow, wr_dcol;  // block stride over (kx, y)            = divmod(threads, ty)
   LineSchedule sch;
   const Tw<T>* tw;
 };
 
 // P2 / P4: transform along the middle index of a tile of lines and transpose.
-// A line u of field f at outer index o is at  base_in + f*fs_in + o*os_in + u*ls_in + p*ps_in.
+// Element p of line u of field f at outer index o is at
+//   in + f*fs_in + o*os_in + u*ls_in + p*ps_in   (elements).
 template <typename T>
 struct YPassParams {
   const cx<T>* in;
   cx<T>* out;
-  i64 in_extent, out_extent;
-  i64 fs_in, os_in, ls_in, ps_in;
-  i64 fs_out, os_out, ls_out, ps_out;
+  i64 fs_in, fs_out;
+  uint32_t in_bytes, out_bytes;  // bytes of one field
+  int os_in, ls_in, ps_in;
+  int os_out, ls_out, ps_out;
   int n;                 // line length
-  int nl;                // lines per tile
+  int nl, nl_last;       // lines per tile (last tile: nl_last)
   int u_lo, u_hi;        // lines processed: [u_lo, u_hi)
-  int utiles;            // tiles along u
+  int utiles, nouter, ntiles;
   int p_lo, p_hi;        // output positions written: [p_lo, p_hi)
+  FastDiv fd_utiles, fd_nouter, fd_n, fd_nl, fd_nl_last, fd_np;
   LineSchedule sch;
   const Tw<T>* tw;
 };
@@ -58,14 +71,17 @@ template <typename T>
 struct ZPushParams {
   cx<T>* b;              // layout B, 11 fields of npts each
   i64 npts;              // NXH * NY * NZ
+  uint32_t field_bytes;  // bytes of one field
   const T* coef;         // C, S1, X1, X2, X3 each npts, pre-scaled by 1/(NX NY NZ)
+  uint32_t coef_bytes;   // bytes of one table
   const T* kx;           // NXH
   const T* ky;           // NY
   const T* kz;           // NZ
-  int NY, NZ, NXH;
+  int NY, NZ, NXH, ncols;
   int z_lo, z_hi;        // output z written: [z_lo, z_hi)
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
+  FastDiv fd_NY;
   LineSchedule sch;
   const Tw<T>* tw;
 };
@@ -75,31 +91,45 @@ struct ZPushParams {
 template <typename T>
 struct XInvParams {
   const cx<T>* src;      // layout A
+  i64 npts;
+  uint32_t src_bytes;    // bytes of one field of A
   T* dst[6];
-  i64 src_extent;
-  i64 dst_extent;        // elements in each destination array
+  uint32_t dst_bytes;    // bytes of each destination array
   int NX, NY, NZ, NXH;
   int ty;                // real y-lines per tile (even)
   int y_lo, y_hi;        // y-lines processed
   int z_lo, z_hi;        // z-planes processed
-  int ytiles;
+  int ytiles, ntiles;
   int scatter;           // 0: dst is box shaped; 1: dst is G1, interior only
   int GX, GY, GZ;
   int ox, oy, oz;        // origin of the interior in G1
   int gx, gy, gz;        // guard widths
   int nx;                // interior cells along x
+  FastDiv fd_ytiles, fd_nz, fd_nc, fd_NX, fd_GX, fd_GY, fd_GZ;
+  int ld_drow, ld_dcol;  // block stride over (kx, complex line) = divmod(threads, ty/2)
+  int wr_drow, wr_dcol;  // block stride over (complex line, x)  = divmod(threads, NX)
   LineSchedule sch;
   const Tw<T>* tw;
 };
 
+// Threads per block of each pass and register budgets of the tile prefetch.
+constexpr int kLineThreads = 512;
 template <typename T>
-void launch_xfwd(const XFwdParams<T>& p, int nfields, int nthreads, hipStream_t s);
+struct prefetch_budget;  // complex values per thread held for the next tile
+template <>
+struct prefetch_budget<float> { static constexpr int v = 12; };
+template <>
+struct prefetch_budget<double> { static constexpr int v = 12; };
+
 template <typename T>
-void launch_ypass(const YPassParams<T>& p, int nfields, int nouter, int inverse, int nthreads, hipStream_t s);
+void launch_xfwd(const XFwdParams<T>& p, hipStream_t s);
+template <typename T>
+void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s);
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s);
 template <typename T>
-void launch_xinv(const XInvParams<T>& p, int nfields, int nthreads, hipStream_t s);
+void launch_xinv(const XInvParams<T>& p, hipStream_t s);
+int zpush_points_per_thread();
 
 // Tables (FP64 math, stored at working precision).
 void launch_twiddles(void* dst, int n, int fp64, hipStream_t s);

@@ -42,8 +42,6 @@ int check_hip(const char* where) {
   return PSATD_OK;
 }
 
-constexpr int kThreads = 256;
-
 // LDS a single workgroup may use on the current device (160 KB per workgroup on
 // gfx950; 64 KB if the query fails).
 size_t lds_limit() {
@@ -56,7 +54,6 @@ size_t lds_limit() {
   return (size_t)v;
 }
 
-inline int lds_stride_h(int n) { return n + ((n & 1) ? 0 : 1); }
 
 // Factor n into compiled radices, largest powers of two first.
 bool make_schedule(int n, int emax, LineSchedule* s) {
@@ -84,14 +81,20 @@ bool make_schedule(int n, int emax, LineSchedule* s) {
   if (r.empty()) r.push_back(1);  // n == 1
   s->nstages = (int)r.size();
   if (n == 1) s->nstages = 0;
-  for (size_t i = 0; i < r.size() && n > 1; ++i) s->radix[i] = r[i];
+  int span = 1;
+  for (size_t i = 0; i < r.size() && n > 1; ++i) {
+    s->radix[i] = r[i];
+    s->bfl[i] = make_fastdiv((uint32_t)(n / r[i]));
+    s->ns[i] = make_fastdiv((uint32_t)span);
+    span *= r[i];
+  }
   return true;
 }
 
 // Largest line count per tile (<= cap) that fits the register budget and `lds` bytes.
 int fit_lines(const LineSchedule& s, int nth, int emax, size_t csize, int cap, size_t lds) {
   for (int nl = cap; nl >= 1; --nl) {
-    bool ok = (size_t)nl * lds_stride_h(s.n) * csize <= lds;
+    bool ok = (size_t)nl * lds_line(s.n) * csize <= lds;
     for (int i = 0; i < s.nstages && ok; ++i) {
       const int R = s.radix[i];
       const long long bf = (long long)nl * (s.n / R);
@@ -117,7 +120,8 @@ struct psatd_plan {
   int fp64 = 0;
   size_t rsize = 0;  // bytes per real
   LineSchedule sx{}, sy{}, sz{};
-  int ty = 0;        // real y-lines per P1/P5 tile
+  int ty1 = 0;       // real y-lines per P1 tile
+  int ty5 = 0;       // real y-lines per P5 tile
   int nl_y = 0;      // lines per P2/P4 tile
   int zthreads = 0;  // threads of the P3 block
   void* twx = nullptr;
@@ -199,23 +203,36 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
     return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d has a prime factor above 17 (not supported by this build)",
                 p->NX, p->NY, p->NZ);
   }
-  // Tiles of the x and y passes stay within 64 KB (several workgroups per CU);
-  // the z pass must hold all 11 lines of a column and may use the device limit.
+  // Tiles of the x and y passes stay within 64 KB (several workgroups per CU)
+  // and within the per-thread prefetch budget; the z pass must hold all 11
+  // lines of a column and may use the device limit.
   const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
-  const int ncx = fit_lines(p->sx, kThreads, em, cs, 8, lds_small);
-  p->ty = 2 * ncx;
-  p->nl_y = fit_lines(p->sy, kThreads, em, cs, 16, lds_small);
+  const int pf = p->fp64 ? prefetch_budget<double>::v : prefetch_budget<float>::v;
+  const int nth = kLineThreads;
+  const int nc1 = std::min(fit_lines(p->sx, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
+  const int nc5 = std::min(fit_lines(p->sx, nth, em, cs, 8, lds_small), ((pf / 2) * nth) / p->NXH);
+  p->ty1 = 2 * std::max(nc1, 0);
+  p->ty5 = 2 * std::max(nc5, 0);
+  p->nl_y = std::min(fit_lines(p->sy, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
   p->zthreads = 0;
-  for (int nth : {256, 512}) {
-    if (fit_lines(p->sz, nth, em, cs, 11, lds_limit()) == 11) {
-      p->zthreads = nth;
+  for (int zt : {nth, 2 * nth}) {
+    const int lines_per_wave = (11 + zt / 64 - 1) / (zt / 64);
+    if (p->NZ <= zpush_points_per_thread() * zt && lines_per_wave * ((p->NZ + 63) / 64) <= pf &&
+        fit_lines(p->sz, zt, em, cs, 11, lds_limit()) == 11) {
+      p->zthreads = zt;
       break;
     }
   }
-  if (p->ty == 0 || p->nl_y == 0 || p->zthreads == 0) {
+  if (p->ty1 <= 0 || p->ty5 <= 0 || p->nl_y <= 0 || p->zthreads == 0) {
     free_plan(p);
     return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d does not fit the LDS / register tiling of this build", p->NX,
                 p->NY, p->NZ);
+  }
+  // Every array is addressed through 32-bit byte offsets.
+  const double field_bytes = (double)p->npts * cs;
+  if (field_bytes >= 4294967296.0 || (double)p->ncell * p->rsize >= 4294967296.0) {
+    free_plan(p);
+    return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d: one field exceeds 4 GiB", p->NX, p->NY, p->NZ);
   }
   const size_t npts = (size_t)p->npts;
   const size_t tws = p->fp64 ? sizeof(Tw<double>) : sizeof(Tw<float>);
@@ -254,13 +271,26 @@ struct StepIO {
   const void* src[11];  // P1 sources
   int gather;
   int GX, GY, GZ, x0, y0, z0;
-  long long src_extent;
+  long long src_elems;  // elements of each source array
   void* dst[6];         // P5 destinations
   int scatter;
   int ox, oy, oz;
-  long long dst_extent;
+  long long dst_elems;  // elements of each destination array
   int y_lo, y_hi, z_lo, z_hi;  // box lines needed after the inverse
 };
+
+template <typename T>
+void set_ypass(YPassParams<T>& y, int nfields) {
+  y.utiles = (y.u_hi - y.u_lo + y.nl - 1) / y.nl;
+  y.nl_last = (y.u_hi - y.u_lo) - (y.utiles - 1) * y.nl;
+  y.ntiles = nfields * y.nouter * y.utiles;
+  y.fd_utiles = make_fastdiv(y.utiles);
+  y.fd_nouter = make_fastdiv(y.nouter);
+  y.fd_n = make_fastdiv(y.n);
+  y.fd_nl = make_fastdiv(y.nl);
+  y.fd_nl_last = make_fastdiv(y.nl_last);
+  y.fd_np = make_fastdiv(y.p_hi - y.p_lo);
+}
 
 // Records event `i` of the current step when timing is on.
 struct Marks {
@@ -274,6 +304,9 @@ struct Marks {
 template <typename T>
 int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   const int NX = p->NX, NY = p->NY, NZ = p->NZ, NXH = p->NXH;
+  const long long npts = p->npts;
+  const uint32_t fbytes = (uint32_t)(npts * (long long)sizeof(cx<T>));
+  const int nth = kLineThreads;
   Marks mk;
   mk.s = s;
   if (p->timing) {
@@ -284,22 +317,23 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
     mk.set = &p->events.back();
   }
   mk.mark(0);
-  const long long npts = p->npts;
   cx<T>* A = (cx<T>*)p->wsA;
   cx<T>* B = (cx<T>*)p->wsB;
   const T* kw = (const T*)p->kw;
 
   XFwdParams<T> x1{};
   for (int f = 0; f < 11; ++f) x1.src[f] = (const T*)io.src[f];
+  x1.src_bytes = (uint32_t)(io.src_elems * (long long)sizeof(T));
   x1.dst = A;
-  x1.src_extent = io.src_extent;
-  x1.dst_extent = 11 * npts;
+  x1.npts = npts;
+  x1.dst_bytes = fbytes;
   x1.NX = NX;
   x1.NY = NY;
   x1.NZ = NZ;
   x1.NXH = NXH;
-  x1.ty = p->ty;
-  x1.ytiles = (NY + p->ty - 1) / p->ty;
+  x1.ty = p->ty1;
+  x1.ytiles = (NY + x1.ty - 1) / x1.ty;
+  x1.ntiles = 11 * NZ * x1.ytiles;
   x1.gather = io.gather;
   x1.GX = io.GX;
   x1.GY = io.GY;
@@ -307,50 +341,68 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x1.x0 = io.x0;
   x1.y0 = io.y0;
   x1.z0 = io.z0;
+  x1.fd_ytiles = make_fastdiv(x1.ytiles);
+  x1.fd_NZ = make_fastdiv(NZ);
+  x1.fd_NX = make_fastdiv(NX);
+  x1.fd_ty = make_fastdiv(x1.ty);
+  if (io.gather) {
+    x1.fd_GX = make_fastdiv(io.GX);
+    x1.fd_GY = make_fastdiv(io.GY);
+    x1.fd_GZ = make_fastdiv(io.GZ);
+  }
+  x1.ld_drow = nth / NX;
+  x1.ld_dcol = nth % NX;
+  x1.wr_drow = nth / x1.ty;
+  x1.wr_dcol = nth % x1.ty;
   x1.sch = p->sx;
   x1.tw = (const Tw<T>*)p->twx;
-  launch_xfwd<T>(x1, 11, kThreads, s);
+  launch_xfwd<T>(x1, s);
   mk.mark(1);
 
   YPassParams<T> y2{};
   y2.in = A;
   y2.out = B;
-  y2.in_extent = 11 * npts;
-  y2.out_extent = 11 * npts;
   y2.fs_in = npts;
-  y2.os_in = NY;
-  y2.ls_in = (long long)NXH * NY;
-  y2.ps_in = 1;
   y2.fs_out = npts;
-  y2.os_out = (long long)NY * NZ;
+  y2.in_bytes = fbytes;
+  y2.out_bytes = fbytes;
+  y2.os_in = NY;
+  y2.ls_in = NXH * NY;
+  y2.ps_in = 1;
+  y2.os_out = NY * NZ;
   y2.ls_out = 1;
   y2.ps_out = NZ;
   y2.n = NY;
   y2.nl = p->nl_y;
   y2.u_lo = 0;
   y2.u_hi = NZ;
-  y2.utiles = (NZ + p->nl_y - 1) / p->nl_y;
+  y2.nouter = NXH;
   y2.p_lo = 0;
   y2.p_hi = NY;
+  set_ypass(y2, 11);
   y2.sch = p->sy;
   y2.tw = (const Tw<T>*)p->twy;
-  launch_ypass<T>(y2, 11, NXH, 0, kThreads, s);
+  launch_ypass<T>(y2, 0, s);
   mk.mark(2);
 
   ZPushParams<T> z3{};
   z3.b = B;
   z3.npts = npts;
+  z3.field_bytes = fbytes;
   z3.coef = (const T*)p->coef;
+  z3.coef_bytes = (uint32_t)(npts * (long long)sizeof(T));
   z3.kx = kw;
   z3.ky = kw + NXH;
   z3.kz = kw + NXH + NY;
   z3.NY = NY;
   z3.NZ = NZ;
   z3.NXH = NXH;
+  z3.ncols = NXH * NY;
   z3.z_lo = io.z_lo;
   z3.z_hi = io.z_hi;
   z3.c2 = T(p->d.c * p->d.c);
   z3.inv_eps0 = T(1.0 / p->d.eps0);
+  z3.fd_NY = make_fastdiv(NY);
   z3.sch = p->sz;
   z3.tw = (const Tw<T>*)p->twz;
   launch_zpush<T>(z3, p->zthreads, s);
@@ -359,43 +411,46 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   YPassParams<T> y4{};
   y4.in = B;
   y4.out = A;
-  y4.in_extent = 11 * npts;
-  y4.out_extent = 11 * npts;
   y4.fs_in = npts;
-  y4.os_in = (long long)NY * NZ;
+  y4.fs_out = npts;
+  y4.in_bytes = fbytes;
+  y4.out_bytes = fbytes;
+  y4.os_in = NY * NZ;
   y4.ls_in = 1;
   y4.ps_in = NZ;
-  y4.fs_out = npts;
   y4.os_out = NY;
-  y4.ls_out = (long long)NXH * NY;
+  y4.ls_out = NXH * NY;
   y4.ps_out = 1;
   y4.n = NY;
   y4.nl = p->nl_y;
   y4.u_lo = io.z_lo;
   y4.u_hi = io.z_hi;
-  y4.utiles = (io.z_hi - io.z_lo + p->nl_y - 1) / p->nl_y;
+  y4.nouter = NXH;
   y4.p_lo = io.y_lo;
   y4.p_hi = io.y_hi;
+  set_ypass(y4, 6);
   y4.sch = p->sy;
   y4.tw = (const Tw<T>*)p->twy;
-  launch_ypass<T>(y4, 6, NXH, 1, kThreads, s);
+  launch_ypass<T>(y4, 1, s);
   mk.mark(4);
 
   XInvParams<T> x5{};
   x5.src = A;
+  x5.npts = npts;
+  x5.src_bytes = fbytes;
   for (int f = 0; f < 6; ++f) x5.dst[f] = (T*)io.dst[f];
-  x5.src_extent = 11 * npts;
-  x5.dst_extent = io.dst_extent;
+  x5.dst_bytes = (uint32_t)(io.dst_elems * (long long)sizeof(T));
   x5.NX = NX;
   x5.NY = NY;
   x5.NZ = NZ;
   x5.NXH = NXH;
-  x5.ty = p->ty;
+  x5.ty = p->ty5;
   x5.y_lo = io.y_lo;
   x5.y_hi = io.y_hi;
   x5.z_lo = io.z_lo;
   x5.z_hi = io.z_hi;
-  x5.ytiles = (io.y_hi - io.y_lo + p->ty - 1) / p->ty;
+  x5.ytiles = (io.y_hi - io.y_lo + x5.ty - 1) / x5.ty;
+  x5.ntiles = 6 * (io.z_hi - io.z_lo) * x5.ytiles;
   x5.scatter = io.scatter;
   x5.GX = io.GX;
   x5.GY = io.GY;
@@ -407,9 +462,22 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x5.gy = p->d.ngy;
   x5.gz = p->d.ngz;
   x5.nx = p->d.nx;
+  x5.fd_ytiles = make_fastdiv(x5.ytiles);
+  x5.fd_nz = make_fastdiv(io.z_hi - io.z_lo);
+  x5.fd_nc = make_fastdiv(x5.ty / 2);
+  x5.fd_NX = make_fastdiv(NX);
+  if (io.scatter) {
+    x5.fd_GX = make_fastdiv(io.GX);
+    x5.fd_GY = make_fastdiv(io.GY);
+    x5.fd_GZ = make_fastdiv(io.GZ);
+  }
+  x5.ld_drow = nth / (x5.ty / 2);
+  x5.ld_dcol = nth % (x5.ty / 2);
+  x5.wr_drow = nth / NX;
+  x5.wr_dcol = nth % NX;
   x5.sch = p->sx;
   x5.tw = (const Tw<T>*)p->twx;
-  launch_xinv<T>(x5, 6, kThreads, s);
+  launch_xinv<T>(x5, s);
   mk.mark(5);
   return check_hip("step kernels");
 }
@@ -534,9 +602,9 @@ int psatd_push(psatd_plan* p, void* const E[3], void* const B[3], const void* co
     io.dst[3 + f] = B[f];
   }
   io.gather = 0;
-  io.src_extent = p->ncell;
+  io.src_elems = p->ncell;
   io.scatter = 0;
-  io.dst_extent = p->ncell;
+  io.dst_elems = p->ncell;
   io.y_lo = 0;
   io.y_hi = p->NY;
   io.z_lo = 0;
@@ -551,6 +619,8 @@ int psatd_step_g1(psatd_plan* p, void* const* g1, const int origin[3], const int
   for (int f = 0; f < 11; ++f)
     if (!g1[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
   if (!distinct(g1, 11)) return fail(PSATD_EINVAL, "field arrays must be distinct");
+  if ((double)gdims[0] * gdims[1] * gdims[2] * p->rsize >= 4294967296.0)
+    return fail(PSATD_EUNSUPPORTED, "global arrays of 4 GiB or more are not supported");
   StepIO io{};
   for (int f = 0; f < 11; ++f) io.src[f] = g1[f];
   for (int f = 0; f < 6; ++f) io.dst[f] = g1[f];
@@ -568,8 +638,8 @@ int psatd_step_g1(psatd_plan* p, void* const* g1, const int origin[3], const int
   io.ox = origin[0];
   io.oy = origin[1];
   io.oz = origin[2];
-  io.src_extent = (long long)gdims[0] * gdims[1] * gdims[2];
-  io.dst_extent = io.src_extent;
+  io.src_elems = (long long)gdims[0] * gdims[1] * gdims[2];
+  io.dst_elems = io.src_elems;
   io.y_lo = p->d.ngy;
   io.y_hi = p->d.ngy + p->d.ny;
   io.z_lo = p->d.ngz;
