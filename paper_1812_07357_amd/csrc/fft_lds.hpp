@@ -136,4 +136,60 @@ __device__ __forceinline__ void lds_fft(cx<T>* lds, int ld, int nlines, const Li
   }
 }
 
+// One line transform as the passes see it: either direct (the stages of
+// `sch` run over the line length n) or Bluestein's chirp-z form for lengths with
+// a prime factor that has no compiled radix.  With c[j] = exp(-i pi j^2 / n),
+//   X[k] = c[k] sum_j (x[j] c[j]) conj(c[k - j]),
+// a linear convolution evaluated as a cyclic one of padded length m >= 2n - 1:
+// premultiply by c, transform (length m), multiply by the transform of the
+// chirp filter b (b[j] = b[m-j] = conj c[j] for 0 <= j < n, zero elsewhere,
+// scaled by 1/m), inverse transform, postmultiply by c.  The inverse DFT uses
+// the conjugate chirp and filter (b is even, so its transform is too).
+template <typename T>
+struct LineFFT {
+  LineSchedule sch;     // stages over the transform length (n, or m for Bluestein)
+  const Tw<T>* tw;      // twiddles of that length
+  int n;                // line length
+  int blue;             // 1: Bluestein, padded length sch.n
+  FastDiv fd_n, fd_m;   // n and sch.n
+  const Tw<T>* chirp;   // n entries c[j]
+  const Tw<T>* filt;    // sch.n entries: transform of b, over m
+};
+
+// LDS slots needed per line by a LineFFT.
+__host__ __device__ __forceinline__ int fft_slots(int transform_len) { return lds_line(transform_len); }
+
+template <int S, typename T>
+__device__ __forceinline__ void lds_line_fft(cx<T>* lds, int ld, int nlines, const LineFFT<T>& L) {
+  if (!L.blue) {
+    lds_fft<S, T>(lds, ld, nlines, L.sch, L.tw);
+    return;
+  }
+  const int n = L.n, m = L.sch.n;
+  const int nth = blockDim.x;
+  for (int e = threadIdx.x; e < nlines * m; e += nth) {
+    const int line = fdiv(e, L.fd_m);
+    const int j = e - line * m;
+    cx<T>* s = lds + line * ld + lpad(j);
+    *s = (j < n) ? twmul<S>(*s, L.chirp[j]) : cx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  lds_fft<-1, T>(lds, ld, nlines, L.sch, L.tw);
+  for (int e = threadIdx.x; e < nlines * m; e += nth) {
+    const int line = fdiv(e, L.fd_m);
+    const int j = e - line * m;
+    cx<T>* s = lds + line * ld + lpad(j);
+    *s = twmul<S>(*s, L.filt[j]);
+  }
+  __syncthreads();
+  lds_fft<1, T>(lds, ld, nlines, L.sch, L.tw);
+  for (int e = threadIdx.x; e < nlines * n; e += nth) {
+    const int line = fdiv(e, L.fd_n);
+    const int j = e - line * n;
+    cx<T>* s = lds + line * ld + lpad(j);
+    *s = twmul<S>(*s, L.chirp[j]);
+  }
+  __syncthreads();
+}
+
 }  // namespace psatd

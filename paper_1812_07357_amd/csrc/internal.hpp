@@ -41,8 +41,7 @@ struct XFwdParams {
   FastDiv fd_ytiles, fd_NZ, fd_NX, fd_GX, fd_GY, fd_GZ, fd_ty;
   int ld_drow, ld_dcol;  // block stride over (complex line, x) = divmod(threads, NX)
   int wr_drow, wr_dcol;  // block stride over (kx, y)            = divmod(threads, ty)
-  LineSchedule sch;
-  const Tw<T>* tw;
+  LineFFT<T> fft;
 };
 
 // P2 / P4: transform along the middle index of a tile of lines and transpose.
@@ -62,8 +61,7 @@ struct YPassParams {
   int utiles, nouter, ntiles;
   int p_lo, p_hi;        // output positions written: [p_lo, p_hi)
   FastDiv fd_utiles, fd_nouter, fd_n, fd_nl, fd_nl_last, fd_np;
-  LineSchedule sch;
-  const Tw<T>* tw;
+  LineFFT<T> fft;
 };
 
 // P3: z-axis forward transform of 11 fields, k-space push, inverse z transform of E, B.
@@ -82,8 +80,7 @@ struct ZPushParams {
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
   FastDiv fd_NY;
-  LineSchedule sch;
-  const Tw<T>* tw;
+  LineFFT<T> fft;
 };
 
 // P5: x-axis complex-to-real inverse of pairs of y-lines from layout A, to box
@@ -108,8 +105,7 @@ struct XInvParams {
   FastDiv fd_ytiles, fd_nz, fd_nc, fd_NX, fd_GX, fd_GY, fd_GZ;
   int ld_drow, ld_dcol;  // block stride over (kx, complex line) = divmod(threads, ty/2)
   int wr_drow, wr_dcol;  // block stride over (complex line, x)  = divmod(threads, NX)
-  LineSchedule sch;
-  const Tw<T>* tw;
+  LineFFT<T> fft;
 };
 
 // Threads per block of each pass and register budgets of the tile prefetch.
@@ -133,6 +129,7 @@ int zpush_points_per_thread();
 
 // Tables (FP64 math, stored at working precision).
 void launch_twiddles(void* dst, int n, int fp64, hipStream_t s);
+void launch_bluestein(void* chirp, void* filt, int n, int m, int fp64, hipStream_t s);
 void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s);
 void launch_coef(void* coef, void* kxw, void* kyw, void* kzw, const double* kx, const double* ky,
                  const double* kz, int NXH, int NY, int NZ, double dt, double c, double norm, int fp64,

@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
   const int NX = p.NX, NY = p.NY, NXH = p.NXH, ty = p.ty, nc = ty >> 1;
-  const int ld = lds_line(NX);
+  const int ld = fft_slots(p.fft.sch.n);
   const int nld = nc * NX;    // complex inputs per tile
   const int nwr = NXH * ty;   // half-spectrum outputs per tile
   Walk w0, v0;
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < p.ntiles) issue(next);
-    lds_fft<-1, T>(lds, ld, nc, p.sch, p.tw);
+    lds_line_fft<-1, T>(lds, ld, nc, p.fft);
 
     // Split each complex line into the half spectra of its two real lines; y fastest.
     const rsrc_t dst = make_rsrc(p.dst + (i64)f * p.npts, p.dst_bytes);
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
   const int n = p.n;
-  const int ld = lds_line(n);
+  const int ld = fft_slots(p.fft.sch.n);
   // block strides of the two walk orders over a tile
   const int pn_drow = fdiv(nth, p.fd_n), pn_dcol = nth - pn_drow * n;  // positions fastest
   cx<T> r[PF];
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < p.ntiles) issue(next);
-    lds_fft<S, T>(lds, ld, nlt, p.sch, p.tw);
+    lds_line_fft<S, T>(lds, ld, nlt, p.fft);
 
     const rsrc_t out = make_rsrc(p.out + (i64)f * p.fs_out, p.out_bytes);
     const int obase = o * p.os_out + u0 * p.ls_out;
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
   const int wave = uniform(tid >> 6);
   const int nwaves = nth >> 6;
   const int NZ = p.NZ;
-  const int ld = lds_line(NZ);
+  const int ld = fft_slots(p.fft.sch.n);
   const int per_line = (NZ + 63) >> 6;
   cx<T> r[PF];
   T cc[kZPts][5], kzv[kZPts];
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
     drain_fields();
     __syncthreads();
     const int next = col + gridDim.x;
-    lds_fft<-1, T>(lds, ld, 11, p.sch, p.tw);
+    lds_line_fft<-1, T>(lds, ld, 11, p.fft);
 
     const int kxi = fdiv(col, p.fd_NY);
     const int kyi = col - kxi * p.NY;
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
       issue_fields(next);
     }
     __syncthreads();
-    lds_fft<1, T>(lds, ld, 6, p.sch, p.tw);
+    lds_line_fft<1, T>(lds, ld, 6, p.fft);
 
     for (int l = wave; l < 6; l += nwaves) {
       const rsrc_t rb = make_rsrc(p.b + (i64)l * p.npts, p.field_bytes);
@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
   const int NX = p.NX, NXH = p.NXH, NY = p.NY, ty = p.ty, nc = ty >> 1;
-  const int ld = lds_line(NX);
+  const int ld = fft_slots(p.fft.sch.n);
   const int nld = nc * NXH;
   const int nwr = nc * NX;
   Walk w0, v0;
@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < p.ntiles) issue(next);
-    lds_fft<1, T>(lds, ld, nc, p.sch, p.tw);
+    lds_line_fft<1, T>(lds, ld, nc, p.fft);
 
     const rsrc_t dst = make_rsrc(p.dst[f], p.dst_bytes);
     const int zrow = p.scatter ? fmod_i(p.oz + z - p.gz, p.fd_GZ) * p.GY : z * NY;
@@ -538,14 +538,14 @@ unsigned persistent_grid(K kernel, int threads, size_t lds, int ntiles) {
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_xfwd(const XFwdParams<T>& p, hipStream_t s) {
-  const size_t lds = (size_t)(p.ty / 2) * lds_line(p.NX) * cx_bytes<T>();
+  const size_t lds = (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
   const unsigned g = persistent_grid(k_xfwd<T>, kLineThreads, lds, p.ntiles);
   hipLaunchKernelGGL(k_xfwd<T>, dim3(g), dim3(kLineThreads), lds, s, p);
 }
 
 template <typename T>
 void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
-  const size_t lds = (size_t)p.nl * lds_line(p.n) * cx_bytes<T>();
+  const size_t lds = (size_t)p.nl * fft_slots(p.fft.sch.n) * cx_bytes<T>();
   if (inverse) {
     const unsigned g = persistent_grid(k_ypass<1, T>, kLineThreads, lds, p.ntiles);
     hipLaunchKernelGGL((k_ypass<1, T>), dim3(g), dim3(kLineThreads), lds, s, p);
@@ -557,7 +557,7 @@ void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
 
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
-  const size_t lds = (size_t)11 * lds_line(p.NZ) * cx_bytes<T>();
+  const size_t lds = (size_t)11 * fft_slots(p.fft.sch.n) * cx_bytes<T>();
   if (nthreads == kLineThreads) {
     const unsigned g = persistent_grid(k_zpush<T, kLineThreads>, nthreads, lds, p.ncols);
     hipLaunchKernelGGL((k_zpush<T, kLineThreads>), dim3(g), dim3(nthreads), lds, s, p);
@@ -569,7 +569,7 @@ void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
 
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
-  const size_t lds = (size_t)(p.ty / 2) * lds_line(p.NX) * cx_bytes<T>();
+  const size_t lds = (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
   const unsigned g = persistent_grid(k_xinv<T>, kLineThreads, lds, p.ntiles);
   hipLaunchKernelGGL(k_xinv<T>, dim3(g), dim3(kLineThreads), lds, s, p);
 }

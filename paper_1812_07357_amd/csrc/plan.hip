@@ -91,6 +91,44 @@ bool make_schedule(int n, int emax, LineSchedule* s) {
   return true;
 }
 
+// One transform axis of a box: direct stages over n, or Bluestein over a padded
+// length m >= 2n - 1 (the smallest m whose factors all have compiled radices).
+struct Axis {
+  int n = 0;
+  int blue = 0;
+  LineSchedule sch{};  // over n, or over m
+  void* tw = nullptr;
+  void* chirp = nullptr;
+  void* filt = nullptr;
+};
+
+bool make_axis(int n, int emax, Axis* a) {
+  a->n = n;
+  a->blue = 0;
+  if (make_schedule(n, emax, &a->sch)) return true;
+  for (int m = 2 * n - 1; m <= 8 * n; ++m) {
+    if (make_schedule(m, emax, &a->sch)) {
+      a->blue = 1;
+      return true;
+    }
+  }
+  return false;
+}
+
+template <typename T>
+LineFFT<T> line_fft(const Axis& a) {
+  LineFFT<T> L{};
+  L.sch = a.sch;
+  L.tw = (const Tw<T>*)a.tw;
+  L.n = a.n;
+  L.blue = a.blue;
+  L.fd_n = make_fastdiv((uint32_t)a.n);
+  L.fd_m = make_fastdiv((uint32_t)a.sch.n);
+  L.chirp = (const Tw<T>*)a.chirp;
+  L.filt = (const Tw<T>*)a.filt;
+  return L;
+}
+
 // Largest line count per tile (<= cap) that fits the register budget and `lds` bytes.
 int fit_lines(const LineSchedule& s, int nth, int emax, size_t csize, int cap, size_t lds) {
   for (int nl = cap; nl >= 1; --nl) {
@@ -119,14 +157,11 @@ struct psatd_plan {
   long long npts = 0, ncell = 0;
   int fp64 = 0;
   size_t rsize = 0;  // bytes per real
-  LineSchedule sx{}, sy{}, sz{};
+  Axis ax, ay, az;   // transform axes x, y, z
   int ty1 = 0;       // real y-lines per P1 tile
   int ty5 = 0;       // real y-lines per P5 tile
   int nl_y = 0;      // lines per P2/P4 tile
   int zthreads = 0;  // threads of the P3 block
-  void* twx = nullptr;
-  void* twy = nullptr;
-  void* twz = nullptr;
   double* kd = nullptr;  // FP64 modified k: kx (NXH), ky (NY), kz (NZ)
   void* kw = nullptr;    // same at working precision
   void* coef = nullptr;  // 5 * npts
@@ -149,7 +184,8 @@ void release_events(psatd_plan* p) {
 void free_plan(psatd_plan* p) {
   if (!p) return;
   release_events(p);
-  void* ptrs[] = {p->twx, p->twy, p->twz, p->kd, p->kw, p->coef, p->wsA, p->wsB};
+  void* ptrs[] = {p->ax.tw, p->ax.chirp, p->ax.filt, p->ay.tw, p->ay.chirp, p->ay.filt, p->az.tw, p->az.chirp,
+                  p->az.filt, p->kd, p->kw, p->coef, p->wsA, p->wsB};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -198,27 +234,29 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   p->rsize = p->fp64 ? 8 : 4;
   const int em = p->fp64 ? emax<double>::v : emax<float>::v;
   const size_t cs = 2 * p->rsize;
-  if (!make_schedule(p->NX, em, &p->sx) || !make_schedule(p->NY, em, &p->sy) || !make_schedule(p->NZ, em, &p->sz)) {
+  if (!make_axis(p->NX, em, &p->ax) || !make_axis(p->NY, em, &p->ay) || !make_axis(p->NZ, em, &p->az)) {
     free_plan(p);
-    return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d has a prime factor above 17 (not supported by this build)",
-                p->NX, p->NY, p->NZ);
+    return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d: no transform schedule", p->NX, p->NY, p->NZ);
   }
+  const LineSchedule& sxs = p->ax.sch;
+  const LineSchedule& sys = p->ay.sch;
+  const LineSchedule& szs = p->az.sch;
   // Tiles of the x and y passes stay within 64 KB (several workgroups per CU)
   // and within the per-thread prefetch budget; the z pass must hold all 11
   // lines of a column and may use the device limit.
   const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
   const int pf = p->fp64 ? prefetch_budget<double>::v : prefetch_budget<float>::v;
   const int nth = kLineThreads;
-  const int nc1 = std::min(fit_lines(p->sx, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
-  const int nc5 = std::min(fit_lines(p->sx, nth, em, cs, 8, lds_small), ((pf / 2) * nth) / p->NXH);
+  const int nc1 = std::min(fit_lines(sxs, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
+  const int nc5 = std::min(fit_lines(sxs, nth, em, cs, 8, lds_small), ((pf / 2) * nth) / p->NXH);
   p->ty1 = 2 * std::max(nc1, 0);
   p->ty5 = 2 * std::max(nc5, 0);
-  p->nl_y = std::min(fit_lines(p->sy, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
+  p->nl_y = std::min(fit_lines(sys, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
   p->zthreads = 0;
   for (int zt : {nth, 2 * nth}) {
     const int lines_per_wave = (11 + zt / 64 - 1) / (zt / 64);
     if (p->NZ <= zpush_points_per_thread() * zt && lines_per_wave * ((p->NZ + 63) / 64) <= pf &&
-        fit_lines(p->sz, zt, em, cs, 11, lds_limit()) == 11) {
+        fit_lines(szs, zt, em, cs, 11, lds_limit()) == 11) {
       p->zthreads = zt;
       break;
     }
@@ -236,9 +274,15 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   }
   const size_t npts = (size_t)p->npts;
   const size_t tws = p->fp64 ? sizeof(Tw<double>) : sizeof(Tw<float>);
-  if ((rc = dalloc(p, &p->twx, tws * p->NX)) || (rc = dalloc(p, &p->twy, tws * p->NY)) ||
-      (rc = dalloc(p, &p->twz, tws * p->NZ)) ||
-      (rc = dalloc(p, (void**)&p->kd, 8 * (size_t)(p->NXH + p->NY + p->NZ))) ||
+  for (Axis* a : {&p->ax, &p->ay, &p->az}) {
+    if ((rc = dalloc(p, &a->tw, tws * a->sch.n)) ||
+        (a->blue && ((rc = dalloc(p, &a->chirp, tws * a->n)) || (rc = dalloc(p, &a->filt, tws * a->sch.n))))) {
+      std::string msg = g_err;
+      free_plan(p);
+      return fail(rc, "%s", msg.c_str());
+    }
+  }
+  if ((rc = dalloc(p, (void**)&p->kd, 8 * (size_t)(p->NXH + p->NY + p->NZ))) ||
       (rc = dalloc(p, &p->kw, p->rsize * (size_t)(p->NXH + p->NY + p->NZ))) ||
       (rc = dalloc(p, &p->coef, 5 * p->rsize * npts)) || (rc = dalloc(p, &p->wsA, 11 * cs * npts)) ||
       (rc = dalloc(p, &p->wsB, 11 * cs * npts))) {
@@ -247,9 +291,10 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
     return fail(rc, "%s", msg.c_str());
   }
   hipStream_t s = nullptr;
-  launch_twiddles(p->twx, p->NX, p->fp64, s);
-  launch_twiddles(p->twy, p->NY, p->fp64, s);
-  launch_twiddles(p->twz, p->NZ, p->fp64, s);
+  for (Axis* a : {&p->ax, &p->ay, &p->az}) {
+    launch_twiddles(a->tw, a->sch.n, p->fp64, s);
+    if (a->blue) launch_bluestein(a->chirp, a->filt, a->n, a->sch.n, p->fp64, s);
+  }
   launch_modk(p->kd, p->NX, p->NXH, d->dx, d->order, s);
   launch_modk(p->kd + p->NXH, p->NY, p->NY, d->dy, d->order, s);
   launch_modk(p->kd + p->NXH + p->NY, p->NZ, p->NZ, d->dz, d->order, s);
@@ -354,8 +399,7 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x1.ld_dcol = nth % NX;
   x1.wr_drow = nth / x1.ty;
   x1.wr_dcol = nth % x1.ty;
-  x1.sch = p->sx;
-  x1.tw = (const Tw<T>*)p->twx;
+  x1.fft = line_fft<T>(p->ax);
   launch_xfwd<T>(x1, s);
   mk.mark(1);
 
@@ -380,8 +424,7 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   y2.p_lo = 0;
   y2.p_hi = NY;
   set_ypass(y2, 11);
-  y2.sch = p->sy;
-  y2.tw = (const Tw<T>*)p->twy;
+  y2.fft = line_fft<T>(p->ay);
   launch_ypass<T>(y2, 0, s);
   mk.mark(2);
 
@@ -403,8 +446,7 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   z3.c2 = T(p->d.c * p->d.c);
   z3.inv_eps0 = T(1.0 / p->d.eps0);
   z3.fd_NY = make_fastdiv(NY);
-  z3.sch = p->sz;
-  z3.tw = (const Tw<T>*)p->twz;
+  z3.fft = line_fft<T>(p->az);
   launch_zpush<T>(z3, p->zthreads, s);
   mk.mark(3);
 
@@ -429,8 +471,7 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   y4.p_lo = io.y_lo;
   y4.p_hi = io.y_hi;
   set_ypass(y4, 6);
-  y4.sch = p->sy;
-  y4.tw = (const Tw<T>*)p->twy;
+  y4.fft = line_fft<T>(p->ay);
   launch_ypass<T>(y4, 1, s);
   mk.mark(4);
 
@@ -475,8 +516,7 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x5.ld_dcol = nth % (x5.ty / 2);
   x5.wr_drow = nth / NX;
   x5.wr_dcol = nth % NX;
-  x5.sch = p->sx;
-  x5.tw = (const Tw<T>*)p->twx;
+  x5.fft = line_fft<T>(p->ax);
   launch_xinv<T>(x5, s);
   mk.mark(5);
   return check_hip("step kernels");

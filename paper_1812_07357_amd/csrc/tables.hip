@@ -42,6 +42,49 @@ __global__ void k_twiddles_f64(Tw<double>* dst, int n) {
   dst[m] = {{c, s}};
 }
 
+// Stores an FP64 complex value as a run-time twiddle of the working precision.
+__device__ inline void put_tw(Tw<float>* dst, int i, double c, double s) {
+  const float ch = (float)c, sh = (float)s;
+  dst[i] = {{ch, sh}, {(float)(c - (double)ch), (float)(s - (double)sh)}};
+}
+__device__ inline void put_tw(Tw<double>* dst, int i, double c, double s) { dst[i] = {{c, s}}; }
+
+// Bluestein chirp c[j] = exp(-i pi j^2 / n); j^2 is reduced modulo 2n exactly.
+template <typename T>
+__global__ void k_chirp(Tw<T>* dst, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const long long q = ((long long)j * j) % (2LL * n);
+  double s, c;
+  sincospi(-(double)q / (double)n, &s, &c);
+  put_tw(dst, j, c, s);
+}
+
+// Bluestein filter F[k] = (1/m) sum_j b[j] exp(-2 pi i j k / m) with b[j] = b[m-j] = conj c[j]
+// for 0 <= j < n and b = 0 elsewhere; direct FP64 sum (m is at most a few hundred).
+template <typename T>
+__global__ void k_bluestein_filter(Tw<T>* dst, int n, int m) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  double re = 0.0, im = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const long long q = ((long long)j * j) % (2LL * n);
+    double bs, bc;
+    sincospi((double)q / (double)n, &bs, &bc);  // b[j] = exp(+i pi j^2 / n)
+    const long long e = ((long long)j * k) % m;
+    double es, ec;
+    sincospi(2.0 * (double)e / (double)m, &es, &ec);
+    // b[j] e^{-2 pi i j k / m}, and for j >= 1 the mirrored tap b[m-j] e^{+2 pi i j k / m}
+    re += bc * ec + bs * es;
+    im += bs * ec - bc * es;
+    if (j >= 1 && 2 * j != m) {
+      re += bc * ec - bs * es;
+      im += bs * ec + bc * es;
+    }
+  }
+  put_tw(dst, k, re / m, im / m);
+}
+
 __global__ void k_modk(double* dst, int n, int count, double d, int order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -120,6 +163,16 @@ void launch_twiddles(void* dst, int n, int fp64, hipStream_t s) {
     hipLaunchKernelGGL(k_twiddles_f64, dim3(nblk(n)), dim3(kT), 0, s, (Tw<double>*)dst, n);
   else
     hipLaunchKernelGGL(k_twiddles_f32, dim3(nblk(n)), dim3(kT), 0, s, (Tw<float>*)dst, n);
+}
+
+void launch_bluestein(void* chirp, void* filt, int n, int m, int fp64, hipStream_t s) {
+  if (fp64) {
+    hipLaunchKernelGGL(k_chirp<double>, dim3(nblk(n)), dim3(kT), 0, s, (Tw<double>*)chirp, n);
+    hipLaunchKernelGGL(k_bluestein_filter<double>, dim3(nblk(m)), dim3(kT), 0, s, (Tw<double>*)filt, n, m);
+  } else {
+    hipLaunchKernelGGL(k_chirp<float>, dim3(nblk(n)), dim3(kT), 0, s, (Tw<float>*)chirp, n);
+    hipLaunchKernelGGL(k_bluestein_filter<float>, dim3(nblk(m)), dim3(kT), 0, s, (Tw<float>*)filt, n, m);
+  }
 }
 
 void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s) {

@@ -47,6 +47,9 @@ def _boxes():
         ((21, 15, 7), 0, 4),         # odd edges 21 x 15 x 7
         ((44, 18, 40), 0, 16),       # box 44 x 18 x 40  (44 = 4 * 11)
         ((9, 13, 33), 1, 2),         # box 11 x 15 x 35  (primes 11, 13-ish mix)
+        ((53, 29, 23), 0, 8),        # prime edges > 17 on every axis (chirp-z transforms)
+        ((219, 40, 60), 2, 32),      # box 223 x 44 x 64: prime x edge of the uneven-box range
+        ((33, 41, 45), 7, 64),       # box 47 x 55 x 59: 47, 59 prime; 55 = 5 * 11
     ]
 
 
