@@ -145,6 +145,46 @@ int psatd_plan_tables(const psatd_plan* plan, void* dst, void* stream);
 int psatd_plan_set_timing(psatd_plan* plan, int enable);
 int psatd_plan_pass_times(psatd_plan* plan, double ms[5], long long* nsteps);
 
+/* ---------------------------------------------------------------- batches
+ * Many sub-domains of one global grid G1, each a box with its own size, guard
+ * width and stencil order (the local decomposition of Fig. 1(a) / Sec. 1.3,
+ * possibly with guards wider than a neighbour, which then come from further
+ * sub-domains).  One step advances every box: all guard fills read the fields
+ * of the previous step before any interior is written back (Jacobi order,
+ * Sec. 2.5.2), and each pass of the step is ONE persistent launch over the
+ * tiles of all boxes.
+ *
+ * subs[b] describes box b (interior sizes, guards, order); dx, dy, dz, dt, c,
+ * eps0 and precision must agree across boxes.  origins[3*b .. 3*b+2] is the
+ * global index of box b's first interior cell; gdims = {GX, GY, GZ}.  The
+ * interiors are meant to tile G1 (not checked); every box interior must fit
+ * in G1.  The batch owns a plan per box (tables and workspace). */
+typedef struct psatd_batch psatd_batch;
+int psatd_batch_create(int nsub, const psatd_plan_desc* subs, const int* origins, const int gdims[3],
+                       psatd_batch** out);
+
+/* One step of every box on the eleven G1 arrays g1[0..10] (E, B updated in
+ * place), launched eagerly on `stream`. */
+int psatd_batch_step(psatd_batch* batch, void* const* g1, void* stream);
+
+/* `nsteps` steps, replayed from a hipGraph that holds nsteps x 5 batched
+ * launches.  The graph is captured on the first call (and again whenever
+ * nsteps or the g1 pointers change), then launched on `stream`.  Results are
+ * identical to nsteps calls of psatd_batch_step.  The sources (J, rho) are
+ * held fixed over the steps. */
+int psatd_batch_run(psatd_batch* batch, void* const* g1, int nsteps, void* stream);
+
+/* Releases a batch (NULL-safe; synchronise its streams first). */
+void psatd_batch_destroy(psatd_batch* batch);
+
+/* Batch properties: PSATD_QB_BOXES, PSATD_QB_TILES (tiles of the five passes
+ * summed), PSATD_QB_BOX_CELLS, PSATD_QB_INTERIOR_CELLS, PSATD_QB_WORKSPACE_BYTES. */
+enum {
+  PSATD_QB_BOXES = 0, PSATD_QB_TILES = 1, PSATD_QB_BOX_CELLS = 2, PSATD_QB_INTERIOR_CELLS = 3,
+  PSATD_QB_WORKSPACE_BYTES = 4
+};
+int psatd_batch_query(const psatd_batch* batch, int what, long long* value);
+
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char* psatd_last_error(void);
 

@@ -75,7 +75,8 @@ struct ZPushParams {
   const T* kx;           // NXH
   const T* ky;           // NY
   const T* kz;           // NZ
-  int NY, NZ, NXH, ncols;
+  int NY, NZ, NXH;
+  int ntiles;            // columns NXH * NY
   int z_lo, z_hi;        // output z written: [z_lo, z_hi)
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
@@ -116,6 +117,34 @@ template <>
 struct prefetch_budget<float> { static constexpr int v = 12; };
 template <>
 struct prefetch_budget<double> { static constexpr int v = 12; };
+
+// A batch of boxes for one pass: per-box parameters in device memory; the tiles
+// of box b are numbered starts[b] .. starts[b+1]-1 (starts[nbox] == total).
+template <typename P>
+struct BatchArgs {
+  const P* descs;
+  const int* starts;
+  int nbox;
+  int total;
+};
+
+template <typename T>
+size_t xfwd_lds(const XFwdParams<T>& p);
+template <typename T>
+size_t ypass_lds(const YPassParams<T>& p);
+template <typename T>
+size_t zpush_lds(const ZPushParams<T>& p);
+template <typename T>
+size_t xinv_lds(const XInvParams<T>& p);
+
+template <typename T>
+void launch_xfwd_batch(const BatchArgs<XFwdParams<T>>& a, size_t lds, hipStream_t s);
+template <typename T>
+void launch_ypass_batch(const BatchArgs<YPassParams<T>>& a, int inverse, size_t lds, hipStream_t s);
+template <typename T>
+void launch_zpush_batch(const BatchArgs<ZPushParams<T>>& a, int nthreads, size_t lds, hipStream_t s);
+template <typename T>
+void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_t s);
 
 template <typename T>
 void launch_xfwd(const XFwdParams<T>& p, hipStream_t s);

@@ -1,10 +1,10 @@
 // The five passes of one PSATD step on a box (gfx950).
 //
-//   P1 k_xfwd   G1 (periodic gather, guard fill fused) or box reals -> x R2C -> layout A
-//   P2 k_ypass  layout A -> y C2C forward -> layout B
-//   P3 k_zpush  layout B -> z C2C forward, analytic push, z C2C inverse -> layout B (E, B)
-//   P4 k_ypass  layout B -> y C2C inverse -> layout A (E, B)
-//   P5 k_xinv   layout A -> x C2R -> box reals or G1 interior (guard merge fused)
+//   P1 xfwd   G1 (periodic gather, guard fill fused) or box reals -> x R2C -> layout A
+//   P2 ypass  layout A -> y C2C forward -> layout B
+//   P3 zpush  layout B -> z C2C forward, analytic push, z C2C inverse -> layout B (E, B)
+//   P4 ypass  layout B -> y C2C inverse -> layout A (E, B)
+//   P5 xinv   layout A -> x C2R -> box reals or G1 interior (guard merge fused)
 //
 // Sec. 1.1 of arXiv:1812.07357 (Fourier transform, analytic k-space update,
 // inverse transform) and Sec. 2.5.2 (fill G2 guards from G1, copy the interior
@@ -17,9 +17,15 @@
 // Every kernel is persistent and software-pipelined: a block loads tile t into
 // registers, moves it to LDS, issues the loads of its next tile (they stay in
 // flight while the LDS transform of tile t runs), writes tile t out, and
-// repeats.  This keeps HBM busy during the LDS phase.  All global accesses go
-// through buffer resources with hardware range checks (gmem.hpp); an index that
-// is out of range by construction (kOOB) reads zero and drops writes.
+// repeats.  All global accesses go through buffer resources with hardware range
+// checks (gmem.hpp); an index that is out of range by construction (kOOB) reads
+// zero and drops writes.
+//
+// Each pass body is written against a parameter source: a single box (the
+// parameters are the kernel argument) or a batch of boxes of different sizes
+// (per-box parameters in device memory, tiles of all boxes numbered one after
+// the other).  A batched launch is one persistent grid over the tiles of every
+// box (Fig. 1(a) of the paper: many sub-domains, each advanced on its own).
 
 #include "internal.hpp"
 
@@ -39,36 +45,63 @@ __device__ inline cx<T>* lds_base() {
 __device__ __forceinline__ int fmod_i(int x, const FastDiv& f) { return x - fdiv(x, f) * (int)f.d; }
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// ------------------------------------------------------------------ parameter sources
+template <typename P>
+struct SingleSrc {
+  const P& p;
+  __device__ __forceinline__ int ntiles() const { return p.ntiles; }
+  __device__ __forceinline__ const P& box(int tile, int& local) const {
+    local = tile;
+    return p;
+  }
+};
+
+template <typename P>
+struct BatchSrc {
+  BatchArgs<P> a;
+  __device__ __forceinline__ int ntiles() const { return a.total; }
+  // box b with starts[b] <= tile < starts[b + 1] (binary search on uniform values)
+  __device__ __forceinline__ const P& box(int tile, int& local) const {
+    int lo = 0, hi = a.nbox;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.starts[mid] <= tile)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    local = tile - a.starts[lo];
+    return a.descs[lo];
+  }
+};
+
 // ------------------------------------------------------------------ P1
-template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
+template <typename T, typename Src>
+__device__ __forceinline__ void xfwd_body(const Src& S) {
   constexpr int PF = prefetch_budget<T>::v;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int NX = p.NX, NY = p.NY, NXH = p.NXH, ty = p.ty, nc = ty >> 1;
-  const int ld = fft_slots(p.fft.sch.n);
-  const int nld = nc * NX;    // complex inputs per tile
-  const int nwr = NXH * ty;   // half-spectrum outputs per tile
-  Walk w0, v0;
-  w0.row = fdiv(tid, p.fd_NX);
-  w0.col = tid - w0.row * NX;
-  v0.row = fdiv(tid, p.fd_ty);
-  v0.col = tid - v0.row * ty;
   T re[PF], im[PF];
 
-  auto decode = [&](int tile, int& f, int& z, int& ybase) {
-    const int q = fdiv(tile, p.fd_ytiles);
-    ybase = (tile - q * p.ytiles) * ty;
+  auto decode = [&](const XFwdParams<T>& p, int lt, int& f, int& z, int& ybase) {
+    const int q = fdiv(lt, p.fd_ytiles);
+    ybase = (lt - q * p.ytiles) * p.ty;
     f = fdiv(q, p.fd_NZ);
     z = q - f * p.NZ;
   };
   auto issue = [&](int tile) {
+    int lt;
+    const XFwdParams<T>& p = S.box(tile, lt);
     int f, z, ybase;
-    decode(tile, f, z, ybase);
+    decode(p, lt, f, z, ybase);
+    const int NX = p.NX, NY = p.NY;
+    const int nld = (p.ty >> 1) * NX;
     const rsrc_t src = make_rsrc(p.src[f], p.src_bytes);
     const int zrow = p.gather ? fmod_i(p.z0 + z, p.fd_GZ) * p.GY : z * NY;
     const int rowlen = p.gather ? p.GX : NX;
-    Walk w = w0;
+    Walk w;
+    w.row = fdiv(tid, p.fd_NX);
+    w.col = tid - w.row * NX;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int e = tid + u * nth;
@@ -91,13 +124,20 @@ __global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
   };
 
   int tile = blockIdx.x;
-  if (tile >= p.ntiles) return;
+  if (tile >= S.ntiles()) return;
   issue(tile);
   for (;;) {
+    int lt;
+    const XFwdParams<T>& p = S.box(tile, lt);
     int f, z, ybase;
-    decode(tile, f, z, ybase);
+    decode(p, lt, f, z, ybase);
+    const int NX = p.NX, NY = p.NY, NXH = p.NXH, ty = p.ty, nc = ty >> 1;
+    const int ld = fft_slots(p.fft.sch.n);
     {
-      Walk w = w0;
+      const int nld = nc * NX;
+      Walk w;
+      w.row = fdiv(tid, p.fd_NX);
+      w.col = tid - w.row * NX;
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         if (tid + u * nth < nld) lds[w.row * ld + lpad(w.col)] = {re[u], im[u]};
@@ -106,13 +146,16 @@ __global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
     }
     __syncthreads();
     const int next = tile + gridDim.x;
-    if (next < p.ntiles) issue(next);
+    if (next < S.ntiles()) issue(next);
     lds_line_fft<-1, T>(lds, ld, nc, p.fft);
 
     // Split each complex line into the half spectra of its two real lines; y fastest.
     const rsrc_t dst = make_rsrc(p.dst + (i64)f * p.npts, p.dst_bytes);
     const int ny_t = min(ty, NY - ybase);
-    Walk v = v0;
+    const int nwr = NXH * ty;
+    Walk v;
+    v.row = fdiv(tid, p.fd_ty);
+    v.col = tid - v.row * ty;
 #pragma unroll 4
     for (int e = tid; e < nwr; e += nth) {
       const int kx = v.row, t = v.col;
@@ -131,65 +174,69 @@ __global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
       v.next(p.wr_drow, p.wr_dcol, ty);
     }
     __syncthreads();
-    if (next >= p.ntiles) break;
+    if (next >= S.ntiles()) break;
     tile = next;
   }
 }
 
 // ------------------------------------------------------------------ P2 / P4
-template <int S, typename T>
-__global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
+template <int S_, typename T, typename Src>
+__device__ __forceinline__ void ypass_body(const Src& S) {
   constexpr int PF = prefetch_budget<T>::v;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int n = p.n;
-  const int ld = fft_slots(p.fft.sch.n);
-  // block strides of the two walk orders over a tile
-  const int pn_drow = fdiv(nth, p.fd_n), pn_dcol = nth - pn_drow * n;  // positions fastest
   cx<T> r[PF];
 
-  auto decode = [&](int tile, int& f, int& o, int& u0, int& nlt, FastDiv& fnl) {
-    const int q = fdiv(tile, p.fd_utiles);
-    const int ut = tile - q * p.utiles;
-    f = fdiv(q, p.fd_nouter);
-    o = q - f * p.nouter;
-    u0 = p.u_lo + ut * p.nl;
-    const bool last = (ut == p.utiles - 1);
-    nlt = last ? p.nl_last : p.nl;
-    fnl = last ? p.fd_nl_last : p.fd_nl;
+  struct Tile {
+    int f, o, u0, nlt;
+    FastDiv fnl;
   };
-  // element e of a tile -> (line t, position q) in the input's preferred order
-  auto start_in = [&](const FastDiv& fnl, int nlt, Walk& w, int& dr, int& dc) {
+  auto decode = [&](const YPassParams<T>& p, int lt) {
+    Tile t;
+    const int q = fdiv(lt, p.fd_utiles);
+    const int ut = lt - q * p.utiles;
+    t.f = fdiv(q, p.fd_nouter);
+    t.o = q - t.f * p.nouter;
+    t.u0 = p.u_lo + ut * p.nl;
+    const bool last = (ut == p.utiles - 1);
+    t.nlt = last ? p.nl_last : p.nl;
+    t.fnl = last ? p.fd_nl_last : p.fd_nl;
+    return t;
+  };
+  // walk over a tile's input elements in the input's preferred order:
+  // positions fastest when lines are contiguous, line index fastest otherwise
+  auto start_in = [&](const YPassParams<T>& p, const Tile& t, Walk& w, int& dr, int& dc, int& ncol) {
     if (p.ps_in == 1) {
       w.row = fdiv(tid, p.fd_n);
-      w.col = tid - w.row * n;
-      dr = pn_drow;
-      dc = pn_dcol;
+      w.col = tid - w.row * p.n;
+      dr = fdiv(nth, p.fd_n);
+      dc = nth - dr * p.n;
+      ncol = p.n;
     } else {
-      w.row = fdiv(tid, fnl);
-      w.col = tid - w.row * nlt;
-      dr = fdiv(nth, fnl);
-      dc = nth - dr * nlt;
+      w.row = fdiv(tid, t.fnl);
+      w.col = tid - w.row * t.nlt;
+      dr = fdiv(nth, t.fnl);
+      dc = nth - dr * t.nlt;
+      ncol = t.nlt;
     }
   };
   auto issue = [&](int tile) {
-    int f, o, u0, nlt;
-    FastDiv fnl;
-    decode(tile, f, o, u0, nlt, fnl);
-    const rsrc_t in = make_rsrc(p.in + (i64)f * p.fs_in, p.in_bytes);
-    const int base = o * p.os_in + u0 * p.ls_in;
-    const int tot = nlt * n;
+    int lt;
+    const YPassParams<T>& p = S.box(tile, lt);
+    const Tile t = decode(p, lt);
+    const rsrc_t in = make_rsrc(p.in + (i64)t.f * p.fs_in, p.in_bytes);
+    const int base = t.o * p.os_in + t.u0 * p.ls_in;
+    const int tot = t.nlt * p.n;
     Walk w;
-    int dr, dc;
-    start_in(fnl, nlt, w, dr, dc);
-    const int ncol = (p.ps_in == 1) ? n : nlt;
+    int dr, dc, ncol;
+    start_in(p, t, w, dr, dc, ncol);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       uint32_t idx = kOOB;
       if (tid + u * nth < tot) {
-        const int t = (p.ps_in == 1) ? w.row : w.col;
+        const int li = (p.ps_in == 1) ? w.row : w.col;
         const int q = (p.ps_in == 1) ? w.col : w.row;
-        idx = (uint32_t)(base + t * p.ls_in + q * p.ps_in);
+        idx = (uint32_t)(base + li * p.ls_in + q * p.ps_in);
       }
       r[u] = gm<T>::ldc(in, idx);
       w.next(dr, dc, ncol);
@@ -197,37 +244,37 @@ __global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
   };
 
   int tile = blockIdx.x;
-  if (tile >= p.ntiles) return;
+  if (tile >= S.ntiles()) return;
   issue(tile);
   for (;;) {
-    int f, o, u0, nlt;
-    FastDiv fnl;
-    decode(tile, f, o, u0, nlt, fnl);
+    int lt;
+    const YPassParams<T>& p = S.box(tile, lt);
+    const Tile t = decode(p, lt);
+    const int ld = fft_slots(p.fft.sch.n);
     {
       Walk w;
-      int dr, dc;
-      start_in(fnl, nlt, w, dr, dc);
-      const int ncol = (p.ps_in == 1) ? n : nlt;
-      const int tot = nlt * n;
+      int dr, dc, ncol;
+      start_in(p, t, w, dr, dc, ncol);
+      const int tot = t.nlt * p.n;
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
         if (tid + u * nth < tot) {
-          const int t = (p.ps_in == 1) ? w.row : w.col;
+          const int li = (p.ps_in == 1) ? w.row : w.col;
           const int q = (p.ps_in == 1) ? w.col : w.row;
-          lds[t * ld + lpad(q)] = r[u];
+          lds[li * ld + lpad(q)] = r[u];
         }
         w.next(dr, dc, ncol);
       }
     }
     __syncthreads();
     const int next = tile + gridDim.x;
-    if (next < p.ntiles) issue(next);
-    lds_line_fft<S, T>(lds, ld, nlt, p.fft);
+    if (next < S.ntiles()) issue(next);
+    lds_line_fft<S_, T>(lds, ld, t.nlt, p.fft);
 
-    const rsrc_t out = make_rsrc(p.out + (i64)f * p.fs_out, p.out_bytes);
-    const int obase = o * p.os_out + u0 * p.ls_out;
+    const rsrc_t out = make_rsrc(p.out + (i64)t.f * p.fs_out, p.out_bytes);
+    const int obase = t.o * p.os_out + t.u0 * p.ls_out;
     const int np = p.p_hi - p.p_lo;
-    const int tot = nlt * np;
+    const int tot = t.nlt * np;
     Walk w;
     int dr, dc, ncol;
     if (p.ps_out == 1) {
@@ -237,21 +284,21 @@ __global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
       dc = nth - dr * np;
       ncol = np;
     } else {
-      w.row = fdiv(tid, fnl);
-      w.col = tid - w.row * nlt;
-      dr = fdiv(nth, fnl);
-      dc = nth - dr * nlt;
-      ncol = nlt;
+      w.row = fdiv(tid, t.fnl);
+      w.col = tid - w.row * t.nlt;
+      dr = fdiv(nth, t.fnl);
+      dc = nth - dr * t.nlt;
+      ncol = t.nlt;
     }
 #pragma unroll 4
     for (int e = tid; e < tot; e += nth) {
-      const int t = (p.ps_out == 1) ? w.row : w.col;
+      const int li = (p.ps_out == 1) ? w.row : w.col;
       const int q = p.p_lo + ((p.ps_out == 1) ? w.col : w.row);
-      gm<T>::stc(out, (uint32_t)(obase + t * p.ls_out + q * p.ps_out), lds[t * ld + lpad(q)]);
+      gm<T>::stc(out, (uint32_t)(obase + li * p.ls_out + q * p.ps_out), lds[li * ld + lpad(q)]);
       w.next(dr, dc, ncol);
     }
     __syncthreads();
-    if (next >= p.ntiles) break;
+    if (next >= S.ntiles()) break;
     tile = next;
   }
 }
@@ -264,30 +311,23 @@ __global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
 // wave's load is uniform and one buffer resource serves it.
 constexpr int kZPts = 2;  // k-space points per thread in the push (NZ <= kZPts * threads)
 
-template <typename T, int NTH>
-__global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
+template <typename T, typename Src>
+__device__ __forceinline__ void zpush_body(const Src& S) {
   constexpr int PF = prefetch_budget<T>::v;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63;
   const int wave = uniform(tid >> 6);
   const int nwaves = nth >> 6;
-  const int NZ = p.NZ;
-  const int ld = fft_slots(p.fft.sch.n);
-  const int per_line = (NZ + 63) >> 6;
   cx<T> r[PF];
-  T cc[kZPts][5], kzv[kZPts];
-#pragma unroll
-  for (int q = 0; q < kZPts; ++q) {
-    const int kz = tid + q * nth;
-    kzv[q] = kz < NZ ? p.kz[kz] : T(0);
-  }
-  rsrc_t ct[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) ct[i] = make_rsrc(p.coef + (i64)i * p.npts, p.coef_bytes);
+  T cc[kZPts][5];
 
   // slot u of the prefetch = (this wave's line number s, chunk i): line wave + s*nwaves, z = lane + 64 i
-  auto issue_fields = [&](int col) {
+  auto issue = [&](int tile) {
+    int col;
+    const ZPushParams<T>& p = S.box(tile, col);
+    const int NZ = p.NZ;
+    const int per_line = (NZ + 63) >> 6;
     int s = 0, i = 0;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
@@ -301,38 +341,39 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
         ++s;
       }
     }
-  };
-  auto drain_fields = [&]() {
-    int s = 0, i = 0;
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int l = wave + s * nwaves;
-      const int z = lane + 64 * i;
-      if (l < 11 && z < NZ) lds[l * ld + lpad(z)] = r[u];
-      if (++i == per_line) {
-        i = 0;
-        ++s;
-      }
-    }
-  };
-  auto issue_coefs = [&](int col) {
 #pragma unroll
     for (int q = 0; q < kZPts; ++q) {
       const int kz = tid + q * nth;
       const uint32_t idx = kz < NZ ? (uint32_t)(col * NZ + kz) : kOOB;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) cc[q][i] = gm<T>::ld(ct[i], idx);
+      for (int c = 0; c < 5; ++c) cc[q][c] = gm<T>::ld(make_rsrc(p.coef + (i64)c * p.npts, p.coef_bytes), idx);
     }
   };
 
-  int col = blockIdx.x;
-  if (col >= p.ncols) return;
-  issue_fields(col);
-  issue_coefs(col);
+  int tile = blockIdx.x;
+  if (tile >= S.ntiles()) return;
+  issue(tile);
   for (;;) {
-    drain_fields();
+    int col;
+    const ZPushParams<T>& p = S.box(tile, col);
+    const int NZ = p.NZ;
+    const int ld = fft_slots(p.fft.sch.n);
+    {
+      const int per_line = (NZ + 63) >> 6;
+      int s = 0, i = 0;
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int l = wave + s * nwaves;
+        const int z = lane + 64 * i;
+        if (l < 11 && z < NZ) lds[l * ld + lpad(z)] = r[u];
+        if (++i == per_line) {
+          i = 0;
+          ++s;
+        }
+      }
+    }
     __syncthreads();
-    const int next = col + gridDim.x;
+    const int next = tile + gridDim.x;
     lds_line_fft<-1, T>(lds, ld, 11, p.fft);
 
     const int kxi = fdiv(col, p.fd_NY);
@@ -345,7 +386,7 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
       const int kz = tid + q * nth;
       if (kz >= NZ) continue;
       const T C = cc[q][0], S1 = cc[q][1], X1 = cc[q][2], X2 = cc[q][3], X3 = cc[q][4];
-      const T kzz = kzv[q];
+      const T kzz = p.kz[kz];
       const int s = lpad(kz);
       const cx<T> ex = lds[0 * ld + s], ey = lds[1 * ld + s], ez = lds[2 * ld + s];
       const cx<T> bx = lds[3 * ld + s], by = lds[4 * ld + s], bz = lds[5 * ld + s];
@@ -383,10 +424,7 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
     }
     // The next column's loads fly during the inverse transform and the stores
     // (issued here rather than before the push to keep the push's registers free).
-    if (next < p.ncols) {
-      issue_coefs(next);
-      issue_fields(next);
-    }
+    if (next < S.ntiles()) issue(next);
     __syncthreads();
     lds_line_fft<1, T>(lds, ld, 6, p.fft);
 
@@ -395,40 +433,37 @@ __global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
       for (int z = p.z_lo + lane; z < p.z_hi; z += 64) gm<T>::stc(rb, (uint32_t)(col * NZ + z), lds[l * ld + lpad(z)]);
     }
     __syncthreads();
-    if (next >= p.ncols) break;
-    col = next;
+    if (next >= S.ntiles()) break;
+    tile = next;
   }
 }
 
 // ------------------------------------------------------------------ P5
-template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
+template <typename T, typename Src>
+__device__ __forceinline__ void xinv_body(const Src& S) {
   constexpr int PF2 = prefetch_budget<T>::v / 2;  // two values per element
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int NX = p.NX, NXH = p.NXH, NY = p.NY, ty = p.ty, nc = ty >> 1;
-  const int ld = fft_slots(p.fft.sch.n);
-  const int nld = nc * NXH;
-  const int nwr = nc * NX;
-  Walk w0, v0;
-  w0.row = fdiv(tid, p.fd_nc);  // (kx, complex line)
-  w0.col = tid - w0.row * nc;
-  v0.row = fdiv(tid, p.fd_NX);  // (complex line, x)
-  v0.col = tid - v0.row * NX;
   cx<T> a[PF2], b[PF2];
 
-  auto decode = [&](int tile, int& f, int& z, int& ybase) {
-    const int q = fdiv(tile, p.fd_ytiles);
-    ybase = p.y_lo + (tile - q * p.ytiles) * ty;
+  auto decode = [&](const XInvParams<T>& p, int lt, int& f, int& z, int& ybase) {
+    const int q = fdiv(lt, p.fd_ytiles);
+    ybase = p.y_lo + (lt - q * p.ytiles) * p.ty;
     f = fdiv(q, p.fd_nz);
     z = p.z_lo + (q - f * (p.z_hi - p.z_lo));
   };
   auto issue = [&](int tile) {
+    int lt;
+    const XInvParams<T>& p = S.box(tile, lt);
     int f, z, ybase;
-    decode(tile, f, z, ybase);
+    decode(p, lt, f, z, ybase);
+    const int NXH = p.NXH, NY = p.NY, nc = p.ty >> 1;
+    const int nld = nc * NXH;
     const rsrc_t src = make_rsrc(p.src + (i64)f * p.npts, p.src_bytes);
     const int sbase = z * NXH * NY;
-    Walk w = w0;
+    Walk w;
+    w.row = fdiv(tid, p.fd_nc);  // (kx, complex line)
+    w.col = tid - w.row * nc;
 #pragma unroll
     for (int u = 0; u < PF2; ++u) {
       uint32_t ia = kOOB, ib = kOOB;
@@ -444,14 +479,21 @@ __global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
   };
 
   int tile = blockIdx.x;
-  if (tile >= p.ntiles) return;
+  if (tile >= S.ntiles()) return;
   issue(tile);
   for (;;) {
+    int lt;
+    const XInvParams<T>& p = S.box(tile, lt);
     int f, z, ybase;
-    decode(tile, f, z, ybase);
+    decode(p, lt, f, z, ybase);
+    const int NX = p.NX, NY = p.NY, nc = p.ty >> 1;
+    const int ld = fft_slots(p.fft.sch.n);
     {
       // Rebuild Z = A + i B over the full line from the half spectra of the two real lines.
-      Walk w = w0;
+      const int nld = nc * p.NXH;
+      Walk w;
+      w.row = fdiv(tid, p.fd_nc);
+      w.col = tid - w.row * nc;
 #pragma unroll
       for (int u = 0; u < PF2; ++u) {
         if (tid + u * nth < nld) {
@@ -470,13 +512,16 @@ __global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
     }
     __syncthreads();
     const int next = tile + gridDim.x;
-    if (next < p.ntiles) issue(next);
+    if (next < S.ntiles()) issue(next);
     lds_line_fft<1, T>(lds, ld, nc, p.fft);
 
     const rsrc_t dst = make_rsrc(p.dst[f], p.dst_bytes);
     const int zrow = p.scatter ? fmod_i(p.oz + z - p.gz, p.fd_GZ) * p.GY : z * NY;
     const int rowlen = p.scatter ? p.GX : NX;
-    Walk v = v0;
+    const int nwr = nc * NX;
+    Walk v;
+    v.row = fdiv(tid, p.fd_NX);  // (complex line, x)
+    v.col = tid - v.row * NX;
 #pragma unroll 4
     for (int e = tid; e < nwr; e += nth) {
       const int c = v.row, n = v.col;
@@ -496,9 +541,43 @@ __global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
       v.next(p.wr_drow, p.wr_dcol, NX);
     }
     __syncthreads();
-    if (next >= p.ntiles) break;
+    if (next >= S.ntiles()) break;
     tile = next;
   }
+}
+
+// ------------------------------------------------------------------ kernels
+template <typename T>
+__global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
+  xfwd_body<T>(SingleSrc<XFwdParams<T>>{p});
+}
+template <typename T>
+__global__ void __launch_bounds__(kLineThreads) k_xfwd_b(BatchArgs<XFwdParams<T>> a) {
+  xfwd_body<T>(BatchSrc<XFwdParams<T>>{a});
+}
+template <int S, typename T>
+__global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
+  ypass_body<S, T>(SingleSrc<YPassParams<T>>{p});
+}
+template <int S, typename T>
+__global__ void __launch_bounds__(kLineThreads) k_ypass_b(BatchArgs<YPassParams<T>> a) {
+  ypass_body<S, T>(BatchSrc<YPassParams<T>>{a});
+}
+template <typename T, int NTH>
+__global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
+  zpush_body<T>(SingleSrc<ZPushParams<T>>{p});
+}
+template <typename T, int NTH>
+__global__ void __launch_bounds__(NTH) k_zpush_b(BatchArgs<ZPushParams<T>> a) {
+  zpush_body<T>(BatchSrc<ZPushParams<T>>{a});
+}
+template <typename T>
+__global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
+  xinv_body<T>(SingleSrc<XInvParams<T>>{p});
+}
+template <typename T>
+__global__ void __launch_bounds__(kLineThreads) k_xinv_b(BatchArgs<XInvParams<T>> a) {
+  xinv_body<T>(BatchSrc<XInvParams<T>>{a});
 }
 
 template <typename T>
@@ -523,7 +602,8 @@ int num_cus() {
 // Opts in to more than 64 KB of dynamic LDS when needed (the plan checked the device limit).
 template <typename K>
 unsigned persistent_grid(K kernel, int threads, size_t lds, int ntiles) {
-  if (lds > 64 * 1024) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1) {
     (void)hipGetLastError();
@@ -533,56 +613,96 @@ unsigned persistent_grid(K kernel, int threads, size_t lds, int ntiles) {
   return (unsigned)(g < ntiles ? g : ntiles);
 }
 
+template <typename K, typename A>
+void launch_persistent(K kernel, const A& arg, int threads, size_t lds, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const unsigned g = persistent_grid(kernel, threads, lds, ntiles);
+  hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), lds, s, arg);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_xfwd(const XFwdParams<T>& p, hipStream_t s) {
-  const size_t lds = (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
-  const unsigned g = persistent_grid(k_xfwd<T>, kLineThreads, lds, p.ntiles);
-  hipLaunchKernelGGL(k_xfwd<T>, dim3(g), dim3(kLineThreads), lds, s, p);
+size_t xfwd_lds(const XFwdParams<T>& p) {
+  return (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+}
+template <typename T>
+size_t ypass_lds(const YPassParams<T>& p) {
+  return (size_t)p.nl * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+}
+template <typename T>
+size_t zpush_lds(const ZPushParams<T>& p) {
+  return (size_t)11 * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+}
+template <typename T>
+size_t xinv_lds(const XInvParams<T>& p) {
+  return (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
 }
 
+template <typename T>
+void launch_xfwd(const XFwdParams<T>& p, hipStream_t s) {
+  launch_persistent(k_xfwd<T>, p, kLineThreads, xfwd_lds(p), p.ntiles, s);
+}
 template <typename T>
 void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
-  const size_t lds = (size_t)p.nl * fft_slots(p.fft.sch.n) * cx_bytes<T>();
-  if (inverse) {
-    const unsigned g = persistent_grid(k_ypass<1, T>, kLineThreads, lds, p.ntiles);
-    hipLaunchKernelGGL((k_ypass<1, T>), dim3(g), dim3(kLineThreads), lds, s, p);
-  } else {
-    const unsigned g = persistent_grid(k_ypass<-1, T>, kLineThreads, lds, p.ntiles);
-    hipLaunchKernelGGL((k_ypass<-1, T>), dim3(g), dim3(kLineThreads), lds, s, p);
-  }
+  if (inverse)
+    launch_persistent(k_ypass<1, T>, p, kLineThreads, ypass_lds(p), p.ntiles, s);
+  else
+    launch_persistent(k_ypass<-1, T>, p, kLineThreads, ypass_lds(p), p.ntiles, s);
 }
-
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
-  const size_t lds = (size_t)11 * fft_slots(p.fft.sch.n) * cx_bytes<T>();
-  if (nthreads == kLineThreads) {
-    const unsigned g = persistent_grid(k_zpush<T, kLineThreads>, nthreads, lds, p.ncols);
-    hipLaunchKernelGGL((k_zpush<T, kLineThreads>), dim3(g), dim3(nthreads), lds, s, p);
-  } else {
-    const unsigned g = persistent_grid(k_zpush<T, 2 * kLineThreads>, nthreads, lds, p.ncols);
-    hipLaunchKernelGGL((k_zpush<T, 2 * kLineThreads>), dim3(g), dim3(nthreads), lds, s, p);
-  }
+  if (nthreads == kLineThreads)
+    launch_persistent(k_zpush<T, kLineThreads>, p, nthreads, zpush_lds(p), p.ntiles, s);
+  else
+    launch_persistent(k_zpush<T, 2 * kLineThreads>, p, nthreads, zpush_lds(p), p.ntiles, s);
+}
+template <typename T>
+void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
+  launch_persistent(k_xinv<T>, p, kLineThreads, xinv_lds(p), p.ntiles, s);
 }
 
 template <typename T>
-void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
-  const size_t lds = (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
-  const unsigned g = persistent_grid(k_xinv<T>, kLineThreads, lds, p.ntiles);
-  hipLaunchKernelGGL(k_xinv<T>, dim3(g), dim3(kLineThreads), lds, s, p);
+void launch_xfwd_batch(const BatchArgs<XFwdParams<T>>& a, size_t lds, hipStream_t s) {
+  launch_persistent(k_xfwd_b<T>, a, kLineThreads, lds, a.total, s);
+}
+template <typename T>
+void launch_ypass_batch(const BatchArgs<YPassParams<T>>& a, int inverse, size_t lds, hipStream_t s) {
+  if (inverse)
+    launch_persistent(k_ypass_b<1, T>, a, kLineThreads, lds, a.total, s);
+  else
+    launch_persistent(k_ypass_b<-1, T>, a, kLineThreads, lds, a.total, s);
+}
+template <typename T>
+void launch_zpush_batch(const BatchArgs<ZPushParams<T>>& a, int nthreads, size_t lds, hipStream_t s) {
+  if (nthreads == kLineThreads)
+    launch_persistent(k_zpush_b<T, kLineThreads>, a, nthreads, lds, a.total, s);
+  else
+    launch_persistent(k_zpush_b<T, 2 * kLineThreads>, a, nthreads, lds, a.total, s);
+}
+template <typename T>
+void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_t s) {
+  launch_persistent(k_xinv_b<T>, a, kLineThreads, lds, a.total, s);
 }
 
 int zpush_points_per_thread() { return kZPts; }
 
-template void launch_xfwd<float>(const XFwdParams<float>&, hipStream_t);
-template void launch_xfwd<double>(const XFwdParams<double>&, hipStream_t);
-template void launch_ypass<float>(const YPassParams<float>&, int, hipStream_t);
-template void launch_ypass<double>(const YPassParams<double>&, int, hipStream_t);
-template void launch_zpush<float>(const ZPushParams<float>&, int, hipStream_t);
-template void launch_zpush<double>(const ZPushParams<double>&, int, hipStream_t);
-template void launch_xinv<float>(const XInvParams<float>&, hipStream_t);
-template void launch_xinv<double>(const XInvParams<double>&, hipStream_t);
+#define PSATD_INSTANTIATE(T)                                                                      \
+  template void launch_xfwd<T>(const XFwdParams<T>&, hipStream_t);                                \
+  template void launch_ypass<T>(const YPassParams<T>&, int, hipStream_t);                         \
+  template void launch_zpush<T>(const ZPushParams<T>&, int, hipStream_t);                         \
+  template void launch_xinv<T>(const XInvParams<T>&, hipStream_t);                                \
+  template void launch_xfwd_batch<T>(const BatchArgs<XFwdParams<T>>&, size_t, hipStream_t);       \
+  template void launch_ypass_batch<T>(const BatchArgs<YPassParams<T>>&, int, size_t, hipStream_t); \
+  template void launch_zpush_batch<T>(const BatchArgs<ZPushParams<T>>&, int, size_t, hipStream_t); \
+  template void launch_xinv_batch<T>(const BatchArgs<XInvParams<T>>&, size_t, hipStream_t);       \
+  template size_t xfwd_lds<T>(const XFwdParams<T>&);                                              \
+  template size_t ypass_lds<T>(const YPassParams<T>&);                                            \
+  template size_t zpush_lds<T>(const ZPushParams<T>&);                                            \
+  template size_t xinv_lds<T>(const XInvParams<T>&);
+PSATD_INSTANTIATE(float)
+PSATD_INSTANTIATE(double)
+#undef PSATD_INSTANTIATE
 
 }  // namespace psatd

@@ -347,26 +347,27 @@ struct Marks {
 };
 
 template <typename T>
-int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
+struct StepParams {
+  XFwdParams<T> x1;
+  YPassParams<T> y2;
+  ZPushParams<T> z3;
+  YPassParams<T> y4;
+  XInvParams<T> x5;
+};
+
+// Kernel parameters of the five passes of one step of plan p with the given inputs / outputs.
+template <typename T>
+void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   const int NX = p->NX, NY = p->NY, NZ = p->NZ, NXH = p->NXH;
   const long long npts = p->npts;
   const uint32_t fbytes = (uint32_t)(npts * (long long)sizeof(cx<T>));
   const int nth = kLineThreads;
-  Marks mk;
-  mk.s = s;
-  if (p->timing) {
-    std::array<hipEvent_t, 6> set{};
-    for (auto& e : set)
-      if (hipEventCreate(&e) != hipSuccess) return check_hip("hipEventCreate");
-    p->events.push_back(set);
-    mk.set = &p->events.back();
-  }
-  mk.mark(0);
   cx<T>* A = (cx<T>*)p->wsA;
   cx<T>* B = (cx<T>*)p->wsB;
   const T* kw = (const T*)p->kw;
 
-  XFwdParams<T> x1{};
+  XFwdParams<T>& x1 = sp.x1;
+  x1 = XFwdParams<T>{};
   for (int f = 0; f < 11; ++f) x1.src[f] = (const T*)io.src[f];
   x1.src_bytes = (uint32_t)(io.src_elems * (long long)sizeof(T));
   x1.dst = A;
@@ -400,10 +401,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x1.wr_drow = nth / x1.ty;
   x1.wr_dcol = nth % x1.ty;
   x1.fft = line_fft<T>(p->ax);
-  launch_xfwd<T>(x1, s);
-  mk.mark(1);
 
-  YPassParams<T> y2{};
+  YPassParams<T>& y2 = sp.y2;
+  y2 = YPassParams<T>{};
   y2.in = A;
   y2.out = B;
   y2.fs_in = npts;
@@ -425,10 +425,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   y2.p_hi = NY;
   set_ypass(y2, 11);
   y2.fft = line_fft<T>(p->ay);
-  launch_ypass<T>(y2, 0, s);
-  mk.mark(2);
 
-  ZPushParams<T> z3{};
+  ZPushParams<T>& z3 = sp.z3;
+  z3 = ZPushParams<T>{};
   z3.b = B;
   z3.npts = npts;
   z3.field_bytes = fbytes;
@@ -440,17 +439,16 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   z3.NY = NY;
   z3.NZ = NZ;
   z3.NXH = NXH;
-  z3.ncols = NXH * NY;
+  z3.ntiles = NXH * NY;
   z3.z_lo = io.z_lo;
   z3.z_hi = io.z_hi;
   z3.c2 = T(p->d.c * p->d.c);
   z3.inv_eps0 = T(1.0 / p->d.eps0);
   z3.fd_NY = make_fastdiv(NY);
   z3.fft = line_fft<T>(p->az);
-  launch_zpush<T>(z3, p->zthreads, s);
-  mk.mark(3);
 
-  YPassParams<T> y4{};
+  YPassParams<T>& y4 = sp.y4;
+  y4 = YPassParams<T>{};
   y4.in = B;
   y4.out = A;
   y4.fs_in = npts;
@@ -472,10 +470,9 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   y4.p_hi = io.y_hi;
   set_ypass(y4, 6);
   y4.fft = line_fft<T>(p->ay);
-  launch_ypass<T>(y4, 1, s);
-  mk.mark(4);
 
-  XInvParams<T> x5{};
+  XInvParams<T>& x5 = sp.x5;
+  x5 = XInvParams<T>{};
   x5.src = A;
   x5.npts = npts;
   x5.src_bytes = fbytes;
@@ -517,7 +514,31 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   x5.wr_drow = nth / NX;
   x5.wr_dcol = nth % NX;
   x5.fft = line_fft<T>(p->ax);
-  launch_xinv<T>(x5, s);
+}
+
+template <typename T>
+int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
+  Marks mk;
+  mk.s = s;
+  if (p->timing) {
+    std::array<hipEvent_t, 6> set{};
+    for (auto& e : set)
+      if (hipEventCreate(&e) != hipSuccess) return check_hip("hipEventCreate");
+    p->events.push_back(set);
+    mk.set = &p->events.back();
+  }
+  StepParams<T> sp;
+  build_step<T>(p, io, sp);
+  mk.mark(0);
+  launch_xfwd<T>(sp.x1, s);
+  mk.mark(1);
+  launch_ypass<T>(sp.y2, 0, s);
+  mk.mark(2);
+  launch_zpush<T>(sp.z3, p->zthreads, s);
+  mk.mark(3);
+  launch_ypass<T>(sp.y4, 1, s);
+  mk.mark(4);
+  launch_xinv<T>(sp.x5, s);
   mk.mark(5);
   return check_hip("step kernels");
 }
@@ -542,6 +563,164 @@ int check_geometry(const psatd_plan* p, const int origin[3], const int gdims[3])
     if (n[a] > gdims[a]) return fail(PSATD_EINVAL, "interior larger than the global grid");
   }
   return PSATD_OK;
+}
+
+// Inputs / outputs of a fused step on G1: gather with wrap, scatter of the interior.
+StepIO g1_io(const psatd_plan* p, void* const* g1, const int origin[3], const int gdims[3]) {
+  StepIO io{};
+  for (int f = 0; f < 11; ++f) io.src[f] = g1[f];
+  for (int f = 0; f < 6; ++f) io.dst[f] = g1[f];
+  io.gather = 1;
+  io.scatter = 1;
+  io.GX = gdims[0];
+  io.GY = gdims[1];
+  io.GZ = gdims[2];
+  const int g[3] = {p->d.ngx, p->d.ngy, p->d.ngz};
+  int st[3];
+  for (int a = 0; a < 3; ++a) st[a] = (int)((((long long)origin[a] - g[a]) % gdims[a] + gdims[a]) % gdims[a]);
+  io.x0 = st[0];
+  io.y0 = st[1];
+  io.z0 = st[2];
+  io.ox = origin[0];
+  io.oy = origin[1];
+  io.oz = origin[2];
+  io.src_elems = (long long)gdims[0] * gdims[1] * gdims[2];
+  io.dst_elems = io.src_elems;
+  io.y_lo = p->d.ngy;
+  io.y_hi = p->d.ngy + p->d.ny;
+  io.z_lo = p->d.ngz;
+  io.z_hi = p->d.ngz + p->d.nz;
+  return io;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- batches
+// A batch keeps one plan per box.  Binding it to a set of G1 arrays builds the
+// kernel parameters of every box for every pass and uploads them, with the
+// tile offsets, to device memory; each pass of a step is then one persistent
+// launch over all boxes (kernels in passes.hip).  Steps can be replayed from a
+// captured hipGraph.
+struct psatd_batch {
+  int nsub = 0;
+  int fp64 = 0;
+  int gd[3] = {0, 0, 0};
+  std::vector<psatd_plan*> plans;
+  std::vector<std::array<int, 3>> origins;
+  void* descs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per-pass parameter arrays
+  int* starts = nullptr;                                           // 5 x (nsub + 1) tile offsets
+  int totals[5] = {0, 0, 0, 0, 0};
+  size_t lds[5] = {0, 0, 0, 0, 0};
+  int zthreads = 0;
+  const void* bound[11] = {};
+  bool is_bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;  // side stream for capture (the null stream cannot be captured)
+  int graph_steps = 0;
+  long long box_cells = 0, interior_cells = 0;
+};
+
+namespace {
+
+void free_batch(psatd_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (void* d : b->descs)
+    if (d) (void)hipFree(d);
+  if (b->starts) (void)hipFree(b->starts);
+  for (psatd_plan* p : b->plans) free_plan(p);
+  delete b;
+}
+
+template <typename P>
+int upload(const std::vector<P>& v, void** dst) {
+  if (*dst) (void)hipFree(*dst);
+  *dst = nullptr;
+  if (hipMalloc(dst, v.size() * sizeof(P)) != hipSuccess) {
+    (void)hipGetLastError();
+    *dst = nullptr;
+    return fail(PSATD_ENOMEM, "batch descriptor allocation failed");
+  }
+  if (hipMemcpy(*dst, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice) != hipSuccess)
+    return check_hip("batch descriptor upload");
+  return PSATD_OK;
+}
+
+template <typename T>
+int bind_batch(psatd_batch* b, void* const* g1) {
+  std::vector<XFwdParams<T>> x1(b->nsub);
+  std::vector<YPassParams<T>> y2(b->nsub), y4(b->nsub);
+  std::vector<ZPushParams<T>> z3(b->nsub);
+  std::vector<XInvParams<T>> x5(b->nsub);
+  std::vector<int> starts(5 * (b->nsub + 1), 0);
+  for (int k = 0; k < 5; ++k) b->lds[k] = 0;
+  b->zthreads = 0;
+  for (int i = 0; i < b->nsub; ++i) {
+    psatd_plan* p = b->plans[i];
+    const StepIO io = g1_io(p, g1, b->origins[i].data(), b->gd);
+    StepParams<T> sp;
+    build_step<T>(p, io, sp);
+    x1[i] = sp.x1;
+    y2[i] = sp.y2;
+    z3[i] = sp.z3;
+    y4[i] = sp.y4;
+    x5[i] = sp.x5;
+    const int nt[5] = {sp.x1.ntiles, sp.y2.ntiles, sp.z3.ntiles, sp.y4.ntiles, sp.x5.ntiles};
+    const size_t ls[5] = {xfwd_lds(sp.x1), ypass_lds(sp.y2), zpush_lds(sp.z3), ypass_lds(sp.y4), xinv_lds(sp.x5)};
+    for (int k = 0; k < 5; ++k) {
+      starts[k * (b->nsub + 1) + i + 1] = starts[k * (b->nsub + 1) + i] + nt[k];
+      b->lds[k] = std::max(b->lds[k], ls[k]);
+    }
+    b->zthreads = std::max(b->zthreads, p->zthreads);
+  }
+  for (int k = 0; k < 5; ++k) b->totals[k] = starts[k * (b->nsub + 1) + b->nsub];
+  int rc;
+  if ((rc = upload(x1, &b->descs[0])) || (rc = upload(y2, &b->descs[1])) || (rc = upload(z3, &b->descs[2])) ||
+      (rc = upload(y4, &b->descs[3])) || (rc = upload(x5, &b->descs[4])))
+    return rc;
+  void* st = b->starts;
+  if ((rc = upload(starts, &st))) return rc;
+  b->starts = (int*)st;
+  for (int f = 0; f < 11; ++f) b->bound[f] = g1[f];
+  b->is_bound = true;
+  return PSATD_OK;
+}
+
+template <typename P>
+BatchArgs<P> batch_args(const psatd_batch* b, int k) {
+  return BatchArgs<P>{(const P*)b->descs[k], b->starts + k * (b->nsub + 1), b->nsub, b->totals[k]};
+}
+
+template <typename T>
+void enqueue_batch_step(const psatd_batch* b, hipStream_t s) {
+  launch_xfwd_batch<T>(batch_args<XFwdParams<T>>(b, 0), b->lds[0], s);
+  launch_ypass_batch<T>(batch_args<YPassParams<T>>(b, 1), 0, b->lds[1], s);
+  launch_zpush_batch<T>(batch_args<ZPushParams<T>>(b, 2), b->zthreads, b->lds[2], s);
+  launch_ypass_batch<T>(batch_args<YPassParams<T>>(b, 3), 1, b->lds[3], s);
+  launch_xinv_batch<T>(batch_args<XInvParams<T>>(b, 4), b->lds[4], s);
+}
+
+int ensure_bound(psatd_batch* b, void* const* g1) {
+  if (!g1) return fail(PSATD_EINVAL, "NULL argument");
+  for (int f = 0; f < 11; ++f)
+    if (!g1[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
+  if (!distinct(g1, 11)) return fail(PSATD_EINVAL, "field arrays must be distinct");
+  bool same = b->is_bound;
+  for (int f = 0; f < 11 && same; ++f) same = (b->bound[f] == g1[f]);
+  if (same) return PSATD_OK;
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->graph_steps = 0;
+  return b->fp64 ? bind_batch<double>(b, g1) : bind_batch<float>(b, g1);
 }
 
 }  // namespace
@@ -717,6 +896,116 @@ int guard_merge(psatd_plan* p, const void* const* box, void* const* g1, int nfie
   const int n[3] = {p->d.nx, p->d.ny, p->d.nz};
   launch_guard_merge(box, g1, nfields, (int)p->rsize, bd, g, n, origin, gdims, mode, (hipStream_t)stream);
   return check_hip("guard_merge");
+}
+
+int psatd_batch_create(int nsub, const psatd_plan_desc* subs, const int* origins, const int gdims[3],
+                       psatd_batch** out) {
+  g_err.clear();
+  if (!out) return fail(PSATD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nsub < 1 || !subs || !origins || !gdims) return fail(PSATD_EINVAL, "bad batch arguments");
+  if ((double)gdims[0] * gdims[1] * gdims[2] * (subs[0].precision == PSATD_FP64 ? 8 : 4) >= 4294967296.0)
+    return fail(PSATD_EUNSUPPORTED, "global arrays of 4 GiB or more are not supported");
+  for (int i = 1; i < nsub; ++i) {
+    const psatd_plan_desc &a = subs[0], &c = subs[i];
+    if (a.precision != c.precision || a.dx != c.dx || a.dy != c.dy || a.dz != c.dz || a.dt != c.dt || a.c != c.c ||
+        a.eps0 != c.eps0)
+      return fail(PSATD_EINVAL, "box %d: precision, cell size, dt, c and eps0 must agree across the batch", i);
+  }
+  psatd_batch* b = new psatd_batch;
+  b->nsub = nsub;
+  b->fp64 = subs[0].precision == PSATD_FP64;
+  for (int a = 0; a < 3; ++a) b->gd[a] = gdims[a];
+  for (int i = 0; i < nsub; ++i) {
+    psatd_plan* p = nullptr;
+    int rc = build_plan(&subs[i], &p);
+    if (rc == PSATD_OK) rc = check_geometry(p, origins + 3 * i, gdims);
+    if (rc != PSATD_OK) {
+      std::string msg = g_err;
+      if (p) free_plan(p);
+      free_batch(b);
+      return fail(rc, "box %d: %s", i, msg.c_str());
+    }
+    b->plans.push_back(p);
+    b->origins.push_back({origins[3 * i], origins[3 * i + 1], origins[3 * i + 2]});
+    b->box_cells += p->ncell;
+    b->interior_cells += (long long)p->d.nx * p->d.ny * p->d.nz;
+  }
+  *out = b;
+  return PSATD_OK;
+}
+
+int psatd_batch_step(psatd_batch* b, void* const* g1, void* stream) {
+  if (!b) return fail(PSATD_EINVAL, "NULL batch");
+  int rc = ensure_bound(b, g1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (b->fp64)
+    enqueue_batch_step<double>(b, s);
+  else
+    enqueue_batch_step<float>(b, s);
+  return check_hip("psatd_batch_step");
+}
+
+int psatd_batch_run(psatd_batch* b, void* const* g1, int nsteps, void* stream) {
+  if (!b) return fail(PSATD_EINVAL, "NULL batch");
+  if (nsteps < 1) return fail(PSATD_EINVAL, "nsteps must be >= 1");
+  int rc = ensure_bound(b, g1);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->exec || b->graph_steps != nsteps) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+      b->cap = nullptr;
+      return check_hip("capture stream");
+    }
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return check_hip("begin capture");
+    for (int i = 0; i < nsteps; ++i) {
+      if (b->fp64)
+        enqueue_batch_step<double>(b, b->cap);
+      else
+        enqueue_batch_step<float>(b, b->cap);
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(b->cap, &g) != hipSuccess || !g) return check_hip("end capture");
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      b->exec = nullptr;
+      return check_hip("graph instantiate");
+    }
+    b->graph_steps = nsteps;
+  }
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) return check_hip("graph launch");
+  return PSATD_OK;
+}
+
+void psatd_batch_destroy(psatd_batch* b) { free_batch(b); }
+
+int psatd_batch_query(const psatd_batch* b, int what, long long* value) {
+  if (!b || !value) return fail(PSATD_EINVAL, "NULL argument");
+  switch (what) {
+    case PSATD_QB_BOXES: *value = b->nsub; break;
+    case PSATD_QB_TILES: {
+      long long t = 0;
+      for (int k = 0; k < 5; ++k) t += b->totals[k];
+      *value = t;
+      break;
+    }
+    case PSATD_QB_BOX_CELLS: *value = b->box_cells; break;
+    case PSATD_QB_INTERIOR_CELLS: *value = b->interior_cells; break;
+    case PSATD_QB_WORKSPACE_BYTES: {
+      long long t = 0;
+      for (const psatd_plan* p : b->plans) t += (long long)p->bytes;
+      *value = t;
+      break;
+    }
+    default: return fail(PSATD_EINVAL, "unknown query %d", what);
+  }
+  return PSATD_OK;
 }
 
 }  // extern "C"

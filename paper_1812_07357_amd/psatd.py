@@ -73,6 +73,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_plan_set_timing.argtypes = [vp, cint]
     lib.psatd_plan_pass_times.restype = cint
     lib.psatd_plan_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    lib.psatd_batch_create.restype = cint
+    lib.psatd_batch_create.argtypes = [cint, ctypes.POINTER(PlanDesc), ip, ip, ctypes.POINTER(vp)]
+    lib.psatd_batch_step.restype = cint
+    lib.psatd_batch_step.argtypes = [vp, vpp, vp]
+    lib.psatd_batch_run.restype = cint
+    lib.psatd_batch_run.argtypes = [vp, vpp, cint, vp]
+    lib.psatd_batch_destroy.restype = None
+    lib.psatd_batch_destroy.argtypes = [vp]
+    lib.psatd_batch_query.restype = cint
+    lib.psatd_batch_query.argtypes = [vp, cint, ctypes.POINTER(ctypes.c_longlong)]
     lib.psatd_last_error.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     return lib
@@ -254,3 +264,71 @@ class Plan:
         coef = buf[: 5 * npts].view(5, nxh, NY, NZ)
         k = buf[5 * npts:]
         return coef, k[:nxh], k[nxh:nxh + NY], k[nxh + NY:]
+
+
+QB_BOXES, QB_TILES, QB_BOX_CELLS, QB_INTERIOR_CELLS, QB_WORKSPACE_BYTES = range(5)
+
+
+class Batch:
+    """Many boxes of one periodic global grid, advanced together (psatd_batch_*).
+
+    ``boxes``: iterable of dicts with ``origin`` (x, y, z), ``interior``
+    (nx, ny, nz), ``nguard`` (scalar or triple) and ``order``; ``gdims`` =
+    (GX, GY, GZ).  Each pass of a step is one persistent launch over all boxes;
+    ``run`` replays ``nsteps`` steps from a captured hipGraph.
+    """
+
+    def __init__(self, boxes, gdims, dx=1.0, dt=0.5, c=1.0, eps0=1.0, precision="fp32"):
+        import torch
+
+        boxes = list(boxes)
+        d = _triple(dx)
+        descs = (PlanDesc * len(boxes))()
+        origins = (ctypes.c_int * (3 * len(boxes)))()
+        for i, b in enumerate(boxes):
+            g = _triple(b["nguard"])
+            n = b["interior"]
+            descs[i] = PlanDesc(int(n[0]), int(n[1]), int(n[2]), int(g[0]), int(g[1]), int(g[2]), int(b["order"]),
+                                float(d[0]), float(d[1]), float(d[2]), float(dt), float(c), float(eps0),
+                                PSATD_FP64 if precision == "fp64" else PSATD_FP32, 0)
+            for a in range(3):
+                origins[3 * i + a] = int(b["origin"][a])
+        h = ctypes.c_void_p()
+        _check(_lib.psatd_batch_create(len(boxes), descs, origins, _ints(gdims), ctypes.byref(h)))
+        self._h = h
+        self.boxes = boxes
+        self.gdims = tuple(int(v) for v in gdims)
+        self.precision = "fp64" if precision == "fp64" else "fp32"
+        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
+
+    def query(self, what: int) -> int:
+        v = ctypes.c_longlong()
+        _check(_lib.psatd_batch_query(self._h, what, ctypes.byref(v)))
+        return int(v.value)
+
+    def _fields(self, g1):
+        f = Plan._split(g1, 11)
+        shape = (self.gdims[2], self.gdims[1], self.gdims[0])
+        for t in f:
+            if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != shape:
+                raise ValueError(f"g1 arrays must be contiguous {self.dtype} GPU tensors of shape {shape}")
+        return f
+
+    def step(self, g1, stream=None):
+        """One step of every box (eager launches)."""
+        _check(_lib.psatd_batch_step(self._h, _ptrs(self._fields(g1)), _stream(stream)))
+
+    def run(self, g1, nsteps: int, stream=None):
+        """``nsteps`` steps replayed from a hipGraph (captured on first use)."""
+        _check(_lib.psatd_batch_run(self._h, _ptrs(self._fields(g1)), int(nsteps), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.psatd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
