@@ -118,6 +118,8 @@ def run_gpu(precision, inputs_host, steps, warmup):
     nx, ny, nz = INTERIOR
     dtype = torch.float64 if precision == "fp64" else torch.float32
     plan = psatd.Plan(nx, ny, nz, nguard=NGUARD, order=ORDER, dx=DX, dt=DT, precision=precision)
+    plan.autotune()
+    schedule = {"xyz"[a]: plan.schedule(a) for a in range(3)}
     g1 = torch.as_tensor(inputs_host, dtype=dtype).to("cuda")
     origin = (0, 0, 0)
     for _ in range(warmup):
@@ -135,7 +137,7 @@ def run_gpu(precision, inputs_host, steps, warmup):
     plan.set_timing(False)
     ms = (t1 - t0) * 1e3 / steps
     res = {"ms_per_step": ms, "passes_ms": passes, "recorded_steps": nrec, "box": plan.box,
-           "workspace_bytes": plan.query(psatd.Q_WORKSPACE_BYTES)}
+           "workspace_bytes": plan.query(psatd.Q_WORKSPACE_BYTES), "schedule": schedule}
     fields = g1[0:6].clone()
     plan.close()
     del g1
@@ -161,6 +163,47 @@ def cpu_baseline():
                       f"(box 288x160x160, same box/interior ratio as the workload), {t:.1f} s"}
 
 
+def run_batch(steps):
+    """64 uneven boxes (edges 32..96 + guards 8..64, orders 16..64), FP32: graph of `steps` steps vs eager."""
+    import torch
+
+    import synth
+    from paper_1812_07357_amd import psatd
+
+    rng = synth.rng_for(3, 0)
+    gdims, boxes = synth.uneven_decomposition(rng)
+    gshape = gdims[::-1]
+    # fields seeded like the 32^3 case: plane waves on the global grid and a Gaussian current
+    pw = synth.plane_wave_modes(synth.rng_for(3, 1), gshape, 4, mmax=8)
+    ev = [synth.transverse_unit(pw["u"][j], pw["m"][j] / np.array(gdims)) for j in range(4)]
+    bv = [np.cross(pw["m"][j] / np.array(gdims), ev[j]) / np.linalg.norm(pw["m"][j] / np.array(gdims))
+          for j in range(4)]
+    E, B = synth.plane_wave_sum(gshape, DX, pw["m"], pw["amp"], pw["phase"], ev, bv)
+    J = synth.gaussian_blob(gshape, DX, tuple(0.5 * g for g in gdims), 3.0, 0.1, (1.0, 0.5, -0.3))
+    host = np.zeros((11,) + gshape, dtype=np.float32)
+    host[0:3], host[3:6], host[6:9] = E, B, J
+    batch = psatd.Batch(boxes, gdims, dx=DX, dt=DT)
+    batch.autotune()
+    g = torch.as_tensor(host, device="cuda")
+    batch.run(g, steps)                     # capture + first replay (warm-up)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run(g, steps)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.step(g)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / steps
+    interior = batch.query(psatd.QB_INTERIOR_CELLS)
+    boxc = batch.query(psatd.QB_BOX_CELLS)
+    batch.close()
+    return {"boxes": len(boxes), "global": list(gdims), "steps_per_graph": steps, "box_cells": boxc,
+            "interior_cell_updates_per_s": interior / t_graph, "box_cell_updates_per_s": boxc / t_graph,
+            "ms_per_step_graph": t_graph * 1e3, "ms_per_step_eager": t_eager * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +211,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -234,6 +278,7 @@ def main():
         "passes_ms_fp32": {k: round(v, 4) for k, v in r32["passes_ms"].items()},
         "step_algorithmic_hbm_frac_fp32": round(step_alg / (r32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "source_digest": digest,
+        "schedule_fp32": r32["schedule"],
     }
 
     if not args.no_fp64:
@@ -257,6 +302,10 @@ def main():
         }
         del f64, e
     del f32
+
+    if not args.no_batch:
+        log("batch run (64 uneven boxes, hipGraph)")
+        out["batch_fp32"] = run_batch(50)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -135,6 +135,22 @@ int psatd_plan_query(const psatd_plan* plan, int what, long long* value);
  * 5*PSATD_Q_SPECTRUM_POINTS + box_x/2+1 + box_y + box_z values. */
 int psatd_plan_tables(const psatd_plan* plan, void* dst, void* stream);
 
+/* Schedule autotuner.  For each axis, times the passes that transform along
+ * it (x: first and last pass, y: second and fourth, z: the k-space pass) for
+ * several radix factorisations / orders of the line length and several tile
+ * sizes on the plan's own workspace, and keeps the fastest.  Results are cached
+ * per (precision, axis, length, other box lengths): in memory for the process,
+ * and in the JSON file `cache_path` if it is not NULL (read first, rewritten
+ * after).  Synchronises `stream`.  Results of later steps are unchanged up to
+ * rounding (the same transform, another factorisation). */
+int psatd_plan_autotune(psatd_plan* plan, const char* cache_path, void* stream);
+
+/* Current schedule of `axis` (0 x, 1 y, 2 z): writes the radix sequence into
+ * radices[0 .. max_radices-1], the tile parameter into *tile (real y-lines
+ * per x tile, lines per y tile, threads of the z pass) and returns the number
+ * of radices (or a negative error). */
+int psatd_plan_schedule(const psatd_plan* plan, int axis, int* radices, int max_radices, int* tile);
+
 /* Per-pass timing for benchmarks.  While enabled, every step records HIP
  * events on its stream before and after each of its five passes (x forward
  * with guard fill, y forward, z forward + push + z inverse, y inverse, x
@@ -176,6 +192,10 @@ int psatd_batch_run(psatd_batch* batch, void* const* g1, int nsteps, void* strea
 
 /* Releases a batch (NULL-safe; synchronise its streams first). */
 void psatd_batch_destroy(psatd_batch* batch);
+
+/* Autotunes every box plan of the batch (see psatd_plan_autotune); the next
+ * step rebuilds the batch's descriptors and graph. */
+int psatd_batch_autotune(psatd_batch* batch, const char* cache_path, void* stream);
 
 /* Batch properties: PSATD_QB_BOXES, PSATD_QB_TILES (tiles of the five passes
  * summed), PSATD_QB_BOX_CELLS, PSATD_QB_INTERIOR_CELLS, PSATD_QB_WORKSPACE_BYTES. */

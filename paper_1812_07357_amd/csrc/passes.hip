@@ -46,13 +46,20 @@ __device__ __forceinline__ int fmod_i(int x, const FastDiv& f) { return x - fdiv
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ------------------------------------------------------------------ parameter sources
+// A single box's parameters are the kernel's only argument, so they sit at
+// offset 0 of the kernel-argument segment.  They are read from there through a
+// pointer: binding a reference to the by-value argument makes the compiler keep
+// a private (scratch) copy of the whole block, because the transform schedules
+// inside it are indexed with run-time stage numbers.
 template <typename P>
 struct SingleSrc {
-  const P& p;
-  __device__ __forceinline__ int ntiles() const { return p.ntiles; }
+  const P* p;
+  __device__ __forceinline__ SingleSrc()
+      : p((const P*)__builtin_amdgcn_kernarg_segment_ptr()) {}
+  __device__ __forceinline__ int ntiles() const { return p->ntiles; }
   __device__ __forceinline__ const P& box(int tile, int& local) const {
     local = tile;
-    return p;
+    return *p;
   }
 };
 
@@ -548,32 +555,32 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
 
 // ------------------------------------------------------------------ kernels
 template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T> p) {
-  xfwd_body<T>(SingleSrc<XFwdParams<T>>{p});
+__global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T>) {
+  xfwd_body<T>(SingleSrc<XFwdParams<T>>{});
 }
 template <typename T>
 __global__ void __launch_bounds__(kLineThreads) k_xfwd_b(BatchArgs<XFwdParams<T>> a) {
   xfwd_body<T>(BatchSrc<XFwdParams<T>>{a});
 }
 template <int S, typename T>
-__global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T> p) {
-  ypass_body<S, T>(SingleSrc<YPassParams<T>>{p});
+__global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T>) {
+  ypass_body<S, T>(SingleSrc<YPassParams<T>>{});
 }
 template <int S, typename T>
 __global__ void __launch_bounds__(kLineThreads) k_ypass_b(BatchArgs<YPassParams<T>> a) {
   ypass_body<S, T>(BatchSrc<YPassParams<T>>{a});
 }
 template <typename T, int NTH>
-__global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T> p) {
-  zpush_body<T>(SingleSrc<ZPushParams<T>>{p});
+__global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T>) {
+  zpush_body<T>(SingleSrc<ZPushParams<T>>{});
 }
 template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) k_zpush_b(BatchArgs<ZPushParams<T>> a) {
   zpush_body<T>(BatchSrc<ZPushParams<T>>{a});
 }
 template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T> p) {
-  xinv_body<T>(SingleSrc<XInvParams<T>>{p});
+__global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T>) {
+  xinv_body<T>(SingleSrc<XInvParams<T>>{});
 }
 template <typename T>
 __global__ void __launch_bounds__(kLineThreads) k_xinv_b(BatchArgs<XInvParams<T>> a) {

@@ -11,6 +11,9 @@
 
 #include <algorithm>
 #include <array>
+#include <cstdlib>
+#include <functional>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -547,6 +550,249 @@ int dispatch_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   return p->fp64 ? run_step<double>(p, io, s) : run_step<float>(p, io, s);
 }
 
+// ---------------------------------------------------------------- autotuner
+// For each axis the tuner times the passes that transform along it (x: P1 + P5,
+// y: P2 + P4, z: P3) for a few radix factorisations / orders of the line
+// length and tile sizes, on the plan's own workspace (contents irrelevant), and
+// keeps the fastest.  Results are cached per (precision, axis role, line
+// length, the two other box lengths) in memory and optionally in a JSON file.
+
+// Radix sequences for n (all factors compiled), at most `cap` of them, the
+// default factorisation first.
+std::vector<std::vector<int>> radix_candidates(int n, int emax, size_t cap) {
+  std::vector<std::vector<int>> out;
+  LineSchedule s;
+  if (!make_schedule(n, emax, &s) || s.nstages == 0) return out;
+  std::vector<int> base(s.radix, s.radix + s.nstages);
+  out.push_back(base);
+  int p2 = 0, m = n;
+  while (m % 2 == 0) {
+    m /= 2;
+    ++p2;
+  }
+  std::vector<int> odd;
+  for (int r : base)
+    if (r % 2) odd.push_back(r);
+  // splits of 2^p2 into 16/8/4/2 factors
+  std::vector<std::vector<int>> splits;
+  const int pw[] = {16, 8, 4, 2};
+  const int lg[] = {4, 3, 2, 1};
+  std::vector<int> cur;
+  std::function<void(int, int)> rec = [&](int left, int start) {
+    if (left == 0) {
+      splits.push_back(cur);
+      return;
+    }
+    for (int i = start; i < 4; ++i)
+      if (lg[i] <= left && pw[i] <= emax) {
+        cur.push_back(pw[i]);
+        rec(left - lg[i], i);
+        cur.pop_back();
+      }
+  };
+  rec(p2, 0);
+  for (auto& sp : splits) {
+    std::vector<int> a = sp, b = odd, c;
+    a.insert(a.end(), odd.begin(), odd.end());  // powers of two first
+    b.insert(b.end(), sp.begin(), sp.end());    // odd radices first
+    c.assign(a.rbegin(), a.rend());             // smallest radices first
+    for (auto* v : {&a, &b, &c})
+      if (std::find(out.begin(), out.end(), *v) == out.end() && out.size() < cap) out.push_back(*v);
+  }
+  return out;
+}
+
+void set_radices(LineSchedule* s, const std::vector<int>& r) {
+  const int n = s->n;
+  std::memset(s, 0, sizeof *s);
+  s->n = n;
+  s->nstages = (int)r.size();
+  int span = 1;
+  for (size_t i = 0; i < r.size(); ++i) {
+    s->radix[i] = r[i];
+    s->bfl[i] = make_fastdiv((uint32_t)(n / r[i]));
+    s->ns[i] = make_fastdiv((uint32_t)span);
+    span *= r[i];
+  }
+}
+
+struct TuneEntry {
+  std::vector<int> radix;
+  int tile = 0;
+};
+std::map<std::string, TuneEntry>& tune_cache() {
+  static std::map<std::string, TuneEntry> c;
+  return c;
+}
+
+void load_tune_file(const char* path) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  // entries look like  "key": {"radix": [16, 4, 5], "tile": 16}
+  size_t pos = 0;
+  while ((pos = text.find("\"radix\"", pos)) != std::string::npos) {
+    const size_t kend = text.rfind('"', text.rfind(':', pos) - 1);
+    const size_t kbeg = text.rfind('"', kend - 1);
+    const std::string key = text.substr(kbeg + 1, kend - kbeg - 1);
+    TuneEntry e;
+    size_t lb = text.find('[', pos), rb = text.find(']', lb);
+    std::string list = text.substr(lb + 1, rb - lb - 1);
+    for (char& ch : list)
+      if (ch == ',') ch = ' ';
+    char* endp = &list[0];
+    for (;;) {
+      char* q = endp;
+      long v = std::strtol(q, &endp, 10);
+      if (endp == q) break;
+      e.radix.push_back((int)v);
+    }
+    const size_t tp = text.find("\"tile\"", rb);
+    e.tile = std::atoi(text.c_str() + text.find(':', tp) + 1);
+    tune_cache()[key] = e;
+    pos = rb;
+  }
+}
+
+void save_tune_file(const char* path) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{\n  \"psatd_tune_cache\": 1,\n  \"entries\": {\n");
+  size_t i = 0;
+  for (auto& kv : tune_cache()) {
+    std::fprintf(f, "    \"%s\": {\"radix\": [", kv.first.c_str());
+    for (size_t j = 0; j < kv.second.radix.size(); ++j)
+      std::fprintf(f, "%s%d", j ? ", " : "", kv.second.radix[j]);
+    std::fprintf(f, "], \"tile\": %d}%s\n", kv.second.tile, ++i < tune_cache().size() ? "," : "");
+  }
+  std::fprintf(f, "  }\n}\n");
+  std::fclose(f);
+}
+
+// Mean milliseconds of `reps` runs of the passes of axis `ax` (0 x, 1 y, 2 z) on scratch data.
+template <typename T>
+float time_axis(psatd_plan* p, int ax, int reps, hipStream_t s) {
+  StepIO io{};
+  T* scratch = (T*)p->wsB;  // box-shaped real arrays for P1 inputs / P5 outputs
+  for (int f = 0; f < 11; ++f) io.src[f] = scratch;
+  for (int f = 0; f < 6; ++f) io.dst[f] = scratch;
+  io.src_elems = io.dst_elems = p->ncell;
+  io.y_lo = 0;
+  io.y_hi = p->NY;
+  io.z_lo = 0;
+  io.z_hi = p->NZ;
+  StepParams<T> sp;
+  build_step<T>(p, io, sp);
+  if (ax == 0) sp.x5.src = (const cx<T>*)p->wsA;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best = 1e30f;
+  for (int pass = 0; pass < 2; ++pass) {  // first pass warms up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) {
+      if (ax == 0) {
+        launch_xfwd<T>(sp.x1, s);
+        launch_xinv<T>(sp.x5, s);
+      } else if (ax == 1) {
+        launch_ypass<T>(sp.y2, 0, s);
+        launch_ypass<T>(sp.y4, 1, s);
+      } else {
+        launch_zpush<T>(sp.z3, p->zthreads, s);
+      }
+    }
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms / reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+template <typename T>
+int autotune_plan(psatd_plan* p, hipStream_t s) {
+  const int em = emax<T>::v;
+  const int pf = prefetch_budget<T>::v;
+  const size_t cs = sizeof(cx<T>);
+  const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
+  const int nth = kLineThreads;
+  const int lens[3] = {p->NX, p->NY, p->NZ};
+  Axis* axes[3] = {&p->ax, &p->ay, &p->az};
+  for (int a = 0; a < 3; ++a) {
+    Axis& A = *axes[a];
+    char key[160];
+    std::snprintf(key, sizeof key, "%s|%c|n=%d|m=%d|other=%dx%d", p->fp64 ? "fp64" : "fp32", "xyz"[a], A.n,
+                  A.sch.n, lens[(a + 1) % 3], lens[(a + 2) % 3]);
+    auto hit = tune_cache().find(key);
+    std::vector<std::vector<int>> cands;
+    std::vector<int> tiles;
+    if (hit != tune_cache().end()) {
+      cands.push_back(hit->second.radix);
+    } else {
+      cands = radix_candidates(A.sch.n, em, 6);
+    }
+    const LineSchedule saved = A.sch;
+    const int saved_tile = a == 0 ? p->ty1 : (a == 1 ? p->nl_y : p->zthreads);
+    float best = 1e30f;
+    TuneEntry best_e{std::vector<int>(saved.radix, saved.radix + saved.nstages), saved_tile};
+    for (auto& r : cands) {
+      set_radices(&A.sch, r);
+      std::vector<int> tl;
+      if (a == 0) {
+        const int hi = std::min(fit_lines(A.sch, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
+        for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(2 * t);
+      } else if (a == 1) {
+        const int hi = std::min(fit_lines(A.sch, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
+        for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(t);
+      } else {
+        for (int zt : {nth, 2 * nth})
+          if (p->NZ <= zpush_points_per_thread() * zt &&
+              ((11 + zt / 64 - 1) / (zt / 64)) * ((p->NZ + 63) / 64) <= pf &&
+              fit_lines(A.sch, zt, em, cs, 11, lds_limit()) == 11)
+            tl.push_back(zt);
+      }
+      if (hit != tune_cache().end()) tl = {hit->second.tile};
+      for (int t : tl) {
+        if (t <= 0) continue;
+        if (a == 0) {
+          p->ty1 = t;
+          p->ty5 = std::min(t, 2 * std::max(1, ((pf / 2) * nth) / p->NXH));
+        } else if (a == 1) {
+          p->nl_y = t;
+        } else {
+          p->zthreads = t;
+        }
+        const float ms = time_axis<T>(p, a, 3, s);
+        if (hipGetLastError() != hipSuccess) continue;
+        if (ms < best) {
+          best = ms;
+          best_e = TuneEntry{r, t};
+        }
+      }
+    }
+    set_radices(&A.sch, best_e.radix);
+    if (a == 0) {
+      p->ty1 = best_e.tile;
+      p->ty5 = std::min(best_e.tile, 2 * std::max(1, ((pf / 2) * nth) / p->NXH));
+    } else if (a == 1) {
+      p->nl_y = best_e.tile;
+    } else {
+      p->zthreads = best_e.tile;
+    }
+    tune_cache()[key] = best_e;
+  }
+  return check_hip("autotune");
+}
+
 bool distinct(const void* const* a, int n) {
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j)
@@ -781,6 +1027,23 @@ int psatd_plan_tables(const psatd_plan* p, void* dst, void* stream) {
   return PSATD_OK;
 }
 
+int psatd_plan_autotune(psatd_plan* p, const char* cache_path, void* stream) {
+  if (!p) return fail(PSATD_EINVAL, "NULL plan");
+  load_tune_file(cache_path);
+  const int rc = p->fp64 ? autotune_plan<double>(p, (hipStream_t)stream) : autotune_plan<float>(p, (hipStream_t)stream);
+  if (rc == PSATD_OK) save_tune_file(cache_path);
+  return rc;
+}
+
+int psatd_plan_schedule(const psatd_plan* p, int axis, int* radices, int max_radices, int* tile) {
+  if (!p || !radices || !tile || axis < 0 || axis > 2) return fail(PSATD_EINVAL, "bad argument");
+  const Axis& A = axis == 0 ? p->ax : (axis == 1 ? p->ay : p->az);
+  if (A.sch.nstages > max_radices) return fail(PSATD_EINVAL, "radix buffer too small");
+  for (int i = 0; i < A.sch.nstages; ++i) radices[i] = A.sch.radix[i];
+  *tile = axis == 0 ? p->ty1 : (axis == 1 ? p->nl_y : p->zthreads);
+  return A.sch.nstages;
+}
+
 int psatd_plan_set_timing(psatd_plan* p, int enable) {
   if (!p) return fail(PSATD_EINVAL, "NULL plan");
   p->timing = enable ? 1 : 0;
@@ -984,6 +1247,25 @@ int psatd_batch_run(psatd_batch* b, void* const* g1, int nsteps, void* stream) {
 }
 
 void psatd_batch_destroy(psatd_batch* b) { free_batch(b); }
+
+int psatd_batch_autotune(psatd_batch* b, const char* cache_path, void* stream) {
+  if (!b) return fail(PSATD_EINVAL, "NULL batch");
+  load_tune_file(cache_path);
+  for (psatd_plan* p : b->plans) {
+    const int rc =
+        p->fp64 ? autotune_plan<double>(p, (hipStream_t)stream) : autotune_plan<float>(p, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  save_tune_file(cache_path);
+  // descriptors and graphs hold the old schedules: rebuild them on the next step
+  b->is_bound = false;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_steps = 0;
+  return PSATD_OK;
+}
 
 int psatd_batch_query(const psatd_batch* b, int what, long long* value) {
   if (!b || !value) return fail(PSATD_EINVAL, "NULL argument");

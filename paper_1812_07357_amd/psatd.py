@@ -73,6 +73,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_plan_set_timing.argtypes = [vp, cint]
     lib.psatd_plan_pass_times.restype = cint
     lib.psatd_plan_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    lib.psatd_plan_autotune.restype = cint
+    lib.psatd_plan_autotune.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.psatd_plan_schedule.restype = cint
+    lib.psatd_plan_schedule.argtypes = [vp, cint, ip, cint, ip]
+    lib.psatd_batch_autotune.restype = cint
+    lib.psatd_batch_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     lib.psatd_batch_create.restype = cint
     lib.psatd_batch_create.argtypes = [cint, ctypes.POINTER(PlanDesc), ip, ip, ctypes.POINTER(vp)]
     lib.psatd_batch_step.restype = cint
@@ -239,6 +245,20 @@ class Plan:
         _check(_lib.guard_merge(self._h, _ptrs(b), _ptrs(g), len(g), _ints(origin), _ints(gdims), int(mode),
                                 _stream(stream)))
 
+    def autotune(self, cache_path=None, stream=None):
+        """Time candidate radix orders / tile sizes per axis and keep the fastest (JSON cache optional)."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(_lib.psatd_plan_autotune(self._h, path, _stream(stream)))
+
+    def schedule(self, axis: int):
+        """(radix sequence, tile parameter) currently used along axis 0 (x), 1 (y) or 2 (z)."""
+        buf = (ctypes.c_int * 16)()
+        tile = ctypes.c_int()
+        n = _lib.psatd_plan_schedule(self._h, int(axis), buf, 16, ctypes.byref(tile))
+        if n < 0:
+            _check(n)
+        return list(buf[:n]), int(tile.value)
+
     PASS_NAMES = ("x_fwd_fill", "y_fwd", "z_push", "y_inv", "x_inv_merge")
 
     def set_timing(self, enable: bool):
@@ -313,6 +333,11 @@ class Batch:
             if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != shape:
                 raise ValueError(f"g1 arrays must be contiguous {self.dtype} GPU tensors of shape {shape}")
         return f
+
+    def autotune(self, cache_path=None, stream=None):
+        """Autotune every box plan (psatd_batch_autotune)."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(_lib.psatd_batch_autotune(self._h, path, _stream(stream)))
 
     def step(self, g1, stream=None):
         """One step of every box (eager launches)."""
