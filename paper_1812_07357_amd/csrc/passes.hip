@@ -578,8 +578,11 @@ template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) k_zpush_b(BatchArgs<ZPushParams<T>> a) {
   zpush_body<T>(BatchSrc<ZPushParams<T>>{a});
 }
+// FP32: capping the registers at 128 (two blocks per CU) is faster for this
+// pass despite a few bytes of spill; the other passes lose more than they gain.
 template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xinv(XInvParams<T>) {
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_xinv(XInvParams<T>) {
   xinv_body<T>(SingleSrc<XInvParams<T>>{});
 }
 template <typename T>
