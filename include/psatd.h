@@ -205,6 +205,75 @@ enum {
 };
 int psatd_batch_query(const psatd_batch* batch, int what, long long* value);
 
+/* ---------------------------------------------------------------- guard-width surrogate
+ * A 6 -> 64 -> 64 -> 1 network that predicts log10 of the truncation error of
+ * a local-with-guards run against the global solve, so that the smallest safe
+ * guard width can be chosen (the paper calls such a model of n_g versus order,
+ * time step and cell size crucial, Sec. 1.4, and ties n_g to memory and cost,
+ * Sec. 2.2).  Inputs per sample (six floats, in this order): 2/p (0 for
+ * infinite order), log2 n_g, c dt/dx, laser wavelength / dx, spectral width
+ * 1/(k0 L), log2 steps.  The network standardises them,
+ * x = (features - in_mean) * in_scale, computes
+ * h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), u = W3 h2 + b3
+ * (silu(z) = z / (1 + exp(-z))) and predicts out_mean + out_scale * u.
+ *
+ * Parameters: PSATD_MLP_NPARAM floats, W1 (64 x 6, row-major out x in), b1
+ * (64), W2 (64 x 64), b2 (64), W3 (64), b3 (1).  The object keeps an FP32
+ * master copy, which Adam updates, and a bfloat16 copy (round to nearest,
+ * ties to even) that prediction and gradients use; activations and sums are
+ * FP32.  Training minimises the mean over the batch of
+ * (u - (target - out_mean) / out_scale)^2.
+ *
+ * All X, target, index, gradient and loss pointers are DEVICE pointers;
+ * X is n x 6 row-major float, targets n floats, idx int32.  Calls are
+ * asynchronous on `stream`, except create/set/get, which synchronise the
+ * device.  One object must not be used on two streams at once. */
+#define PSATD_MLP_NPARAM 4673
+typedef struct psatd_mlp psatd_mlp;
+
+/* Creates a network from `init` (host, PSATD_MLP_NPARAM floats), the
+ * standardisation constants (host, 6 floats each) and the output affine map;
+ * `max_batch` bounds the batch of psatd_mlp_grad / psatd_mlp_train.  Adam's
+ * moments start at zero. */
+int psatd_mlp_create(const float* init, const float* in_mean, const float* in_scale, float out_mean,
+                     float out_scale, int max_batch, psatd_mlp** out);
+
+/* Replaces the master weights (host array), re-rounds the bfloat16 copy and
+ * resets Adam (moments and step count). */
+int psatd_mlp_set(psatd_mlp* mlp, const float* master);
+
+/* Copies the master weights and/or the bfloat16 copy (as raw 16-bit
+ * patterns) to host arrays; either may be NULL. */
+int psatd_mlp_get(const psatd_mlp* mlp, float* master, unsigned short* bf16);
+
+/* y[i] = prediction for X[i], i < n (n = 0 is a no-op). */
+int psatd_mlp_predict(const psatd_mlp* mlp, const float* X, int n, float* y, void* stream);
+
+/* Gradient of the batch loss with respect to the (bfloat16) weights.  The
+ * batch is samples idx[0 .. batch-1] of X / target (idx NULL: samples
+ * 0 .. batch-1, which requires batch <= n); an index outside [0, n)
+ * contributes nothing.  The gradient (PSATD_MLP_NPARAM floats) and the loss
+ * (1 float) are kept in the object and also copied to `grad` / `loss` when
+ * these are not NULL.  The sums run in a fixed order, so results are
+ * reproducible. */
+int psatd_mlp_grad(psatd_mlp* mlp, const float* X, const float* target, int n, const int* idx, int batch,
+                   float* grad, float* loss, void* stream);
+
+/* One Adam step (Kingma & Ba, 2015, with bias correction) from the gradient
+ * of the last psatd_mlp_grad, on the master weights; the bfloat16 copy is
+ * refreshed. */
+int psatd_mlp_adam(psatd_mlp* mlp, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* `nsteps` steps of minibatch training: step k takes the batch
+ * idx[k*batch .. k*batch + batch - 1] (idx NULL: the first `batch` samples
+ * every step), computes the gradient and applies Adam.  The batch loss of
+ * every step (before its update) goes to loss_hist[k] when not NULL. */
+int psatd_mlp_train(psatd_mlp* mlp, const float* X, const float* target, int n, const int* idx, int nsteps,
+                    int batch, float lr, float beta1, float beta2, float eps, float* loss_hist, void* stream);
+
+/* Releases the network (NULL-safe; synchronise its stream first). */
+void psatd_mlp_destroy(psatd_mlp* mlp);
+
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char* psatd_last_error(void);
 

@@ -31,7 +31,7 @@ FLAGS = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
-SOURCES = ["passes.hip", "tables.hip", "guards.hip", "plan.hip"]
+SOURCES = ["passes.hip", "tables.hip", "guards.hip", "plan.hip", "mlp.hip"]
 
 
 def _compile(src: str) -> str:

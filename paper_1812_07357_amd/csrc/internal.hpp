@@ -171,4 +171,7 @@ void launch_guard_merge(const void* const* box, void* const* g1, int nfields, in
                         const int guard[3], const int interior[3], const int origin[3], const int gdims[3],
                         int mode, hipStream_t s);
 
+// Records a message for psatd_last_error() and returns `code`.
+int report_error(int code, const char* fmt, ...);
+
 }  // namespace psatd

@@ -972,6 +972,17 @@ int ensure_bound(psatd_batch* b, void* const* g1) {
 }  // namespace
 
 // ================================================================ C ABI
+// Error reporting for the other translation units of the library.
+int psatd::report_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
 extern "C" {
 
 const char* psatd_last_error(void) { return g_err.c_str(); }

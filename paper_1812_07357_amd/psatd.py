@@ -45,7 +45,15 @@ class PsatdError(RuntimeError):
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
-    """dlopen libpsatd.so and declare the C signatures (no GPU needed)."""
+    """dlopen libpsatd.so and declare the C signatures (no GPU needed).
+
+    torch is imported first: it carries its own HIP runtime under the same
+    soname as the system one, and the library must bind to the runtime that
+    owns torch's device memory and streams (two runtimes in one process do not
+    share allocations or contexts).
+    """
+    import torch  # noqa: F401  (load order: torch's HIP runtime first)
+
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1812_07357_amd.build_lib`")
     lib = ctypes.CDLL(path)
@@ -89,6 +97,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_batch_destroy.argtypes = [vp]
     lib.psatd_batch_query.restype = cint
     lib.psatd_batch_query.argtypes = [vp, cint, ctypes.POINTER(ctypes.c_longlong)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    cf = ctypes.c_float
+    lib.psatd_mlp_create.restype = cint
+    lib.psatd_mlp_create.argtypes = [fp, fp, fp, cf, cf, cint, ctypes.POINTER(vp)]
+    lib.psatd_mlp_set.restype = cint
+    lib.psatd_mlp_set.argtypes = [vp, fp]
+    lib.psatd_mlp_get.restype = cint
+    lib.psatd_mlp_get.argtypes = [vp, fp, ctypes.POINTER(ctypes.c_ushort)]
+    lib.psatd_mlp_predict.restype = cint
+    lib.psatd_mlp_predict.argtypes = [vp, vp, cint, vp, vp]
+    lib.psatd_mlp_grad.restype = cint
+    lib.psatd_mlp_grad.argtypes = [vp, vp, vp, cint, vp, cint, vp, vp, vp]
+    lib.psatd_mlp_adam.restype = cint
+    lib.psatd_mlp_adam.argtypes = [vp, cf, cf, cf, cf, vp]
+    lib.psatd_mlp_train.restype = cint
+    lib.psatd_mlp_train.argtypes = [vp, vp, vp, cint, vp, cint, cint, cf, cf, cf, cf, vp, vp]
+    lib.psatd_mlp_destroy.restype = None
+    lib.psatd_mlp_destroy.argtypes = [vp]
     lib.psatd_last_error.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     return lib
@@ -350,6 +376,125 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.psatd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MLP_NPARAM = 4673
+
+
+class Mlp:
+    """Guard-width surrogate network (psatd_mlp_*): 6 -> 64 -> 64 -> 1, SiLU, bfloat16 weights.
+
+    ``init``: MLP_NPARAM initial FP32 parameters (W1, b1, W2, b2, W3, b3);
+    ``in_mean`` / ``in_scale``: per-feature standardisation; ``out_mean`` /
+    ``out_scale``: affine map of the network output to log10 error.
+    Every tensor argument is a contiguous GPU tensor (float32 features
+    (n, 6) and targets (n,), int32 indices).
+    """
+
+    def __init__(self, init, in_mean, in_scale, out_mean=0.0, out_scale=1.0, max_batch=4096):
+        import numpy as np
+
+        init = np.ascontiguousarray(init, dtype=np.float32)
+        if init.shape != (MLP_NPARAM,):
+            raise ValueError(f"init must hold {MLP_NPARAM} values")
+        mean = np.ascontiguousarray(in_mean, dtype=np.float32).reshape(6)
+        scale = np.ascontiguousarray(in_scale, dtype=np.float32).reshape(6)
+        fp = ctypes.POINTER(ctypes.c_float)
+        h = ctypes.c_void_p()
+        _check(_lib.psatd_mlp_create(init.ctypes.data_as(fp), mean.ctypes.data_as(fp), scale.ctypes.data_as(fp),
+                                     float(out_mean), float(out_scale), int(max_batch), ctypes.byref(h)))
+        self._h = h
+        self.max_batch = int(max_batch)
+        self.norm = (mean.copy(), scale.copy(), float(out_mean), float(out_scale))
+
+    @staticmethod
+    def _gpu(t, dtype, shape=None, name="tensor"):
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} GPU tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _xt(self, X, t=None):
+        import torch
+
+        if X.dim() != 2 or X.shape[1] != 6:
+            raise ValueError("features must have shape (n, 6)")
+        n = int(X.shape[0])
+        px = self._gpu(X, torch.float32, name="features")
+        pt = None if t is None else self._gpu(t, torch.float32, (n,), "targets")
+        return n, px, pt
+
+    def set_params(self, master):
+        import numpy as np
+
+        m = np.ascontiguousarray(master, dtype=np.float32)
+        if m.shape != (MLP_NPARAM,):
+            raise ValueError(f"parameters must hold {MLP_NPARAM} values")
+        _check(_lib.psatd_mlp_set(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def params(self):
+        """(FP32 master weights, bfloat16 copy as float32) as numpy arrays (synchronises)."""
+        import numpy as np
+
+        m = np.empty(MLP_NPARAM, dtype=np.float32)
+        b = np.empty(MLP_NPARAM, dtype=np.uint16)
+        _check(_lib.psatd_mlp_get(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  b.ctypes.data_as(ctypes.POINTER(ctypes.c_ushort))))
+        return m, (b.astype(np.uint32) << 16).view(np.float32)
+
+    def predict(self, X, stream=None):
+        import torch
+
+        n, px, _ = self._xt(X)
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+        _check(_lib.psatd_mlp_predict(self._h, px, n, ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+        return y
+
+    def grad(self, X, t, idx=None, batch=None, stream=None):
+        """(gradient (MLP_NPARAM,), loss) of the batch as GPU tensors."""
+        import torch
+
+        n, px, pt = self._xt(X, t)
+        pi = None
+        if idx is not None:
+            pi = self._gpu(idx, torch.int32, name="idx")
+            batch = int(idx.numel()) if batch is None else int(batch)
+        batch = n if batch is None else int(batch)
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(_lib.psatd_mlp_grad(self._h, px, pt, n, pi, batch, ctypes.c_void_p(g.data_ptr()),
+                                   ctypes.c_void_p(loss.data_ptr()), _stream(stream)))
+        return g, loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.psatd_mlp_adam(self._h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def train(self, X, t, idx, nsteps, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """``nsteps`` Adam steps on minibatches idx[k*batch:(k+1)*batch]; returns the per-step loss (GPU)."""
+        import torch
+
+        n, px, pt = self._xt(X, t)
+        pi = None
+        if idx is not None:
+            if idx.numel() < int(nsteps) * int(batch):
+                raise ValueError("idx must hold nsteps * batch indices")
+            pi = self._gpu(idx, torch.int32, name="idx")
+        hist = torch.empty(max(1, int(nsteps)), dtype=torch.float32, device=X.device)
+        _check(_lib.psatd_mlp_train(self._h, px, pt, n, pi, int(nsteps), int(batch), lr, beta1, beta2, eps,
+                                    ctypes.c_void_p(hist.data_ptr()), _stream(stream)))
+        return hist[: int(nsteps)]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.psatd_mlp_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

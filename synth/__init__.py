@@ -17,6 +17,7 @@ from .fields import (  # noqa: F401
     transverse_unit,
     gaussian_blob,
     laser_pulse,
+    laser_modes,
     macro_particle_deposit,
     uneven_decomposition,
 )

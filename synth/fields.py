@@ -94,6 +94,46 @@ def plane_wave_sum(shape, d, m, amp, phase, evec, bvec, omega=None, t: float = 0
     return E, B
 
 
+def laser_modes(rng: np.random.Generator, shape, d: float, wavelength: float, width: float, nmodes: int = 16,
+                transverse: float = 0.6, c: float = 1.0):
+    """A laser-like vacuum wave packet as a sum of grid plane waves, for ``plane_wave_sum``.
+
+    Mode numbers are drawn around the grid mode of the laser wavenumber
+    k0 = 2 pi / wavelength along +x: m_x ~ round(N(m0, (width * m0)^2)) with
+    m0 = N_x d / wavelength (width = 1 / (k0 L), the relative spectral width),
+    m_y, m_z ~ round(N(0, transverse^2)); duplicates, the zero mode and
+    Nyquist indices are rejected (at most ``nmodes`` distinct modes are kept).
+    Phases -k . x_c put every mode's crest at one random centre x_c, so the
+    modes add up to a pulse there.  Polarisation: the part of y-hat orthogonal
+    to k; B = k-hat x E / c (forward propagation).  Equal amplitudes
+    1 / sqrt(number of modes).
+    """
+    nz, ny, nx = shape
+    lim = np.array([(nx - 1) // 2, (ny - 1) // 2, (nz - 1) // 2])
+    m0 = nx * d / wavelength
+    sx = max(width * m0, 1e-3)
+    seen, modes = set(), []
+    for _ in range(50 * nmodes):
+        if len(modes) == nmodes:
+            break
+        m = (int(np.rint(rng.normal(m0, sx))), int(np.rint(rng.normal(0.0, transverse))),
+             int(np.rint(rng.normal(0.0, transverse))))
+        if m in seen or m[0] <= 0 or abs(m[0]) > lim[0] or abs(m[1]) > lim[1] or abs(m[2]) > lim[2]:
+            continue
+        seen.add(m)
+        modes.append(m)
+    m = np.array(modes, dtype=np.int64)
+    n = len(modes)
+    centre = rng.uniform(0.0, 1.0, size=3) * np.array([nx, ny, nz]) * d
+    kvec = 2.0 * np.pi * m / (np.array([nx, ny, nz]) * d)
+    phase = -(kvec @ centre)
+    evec = np.array([transverse_unit((0.0, 1.0, 0.0), k) for k in kvec])
+    khat = kvec / np.linalg.norm(kvec, axis=1, keepdims=True)
+    bvec = np.cross(khat, evec) / c
+    return {"m": m, "amp": np.full(n, 1.0 / np.sqrt(n)), "phase": phase, "evec": evec, "bvec": bvec,
+            "centre": centre}
+
+
 def gaussian_blob(shape, d, center, sigma: float, amplitude: float, direction):
     """Vector field amplitude * direction * exp(-|x - center|^2 / (2 sigma^2)), (3, Nz, Ny, Nx).
 

@@ -67,3 +67,24 @@ def test_null_arguments(lib):
     assert L.psatd_plan_query(None, 0, ctypes.byref(v)) == lib.PSATD_EINVAL
     L.psatd_plan_destroy(None)  # NULL-safe
     assert L.psatd_plan_create(0, 8, 8, 0, 0, 1.0, 0.5) is None
+
+
+def test_mlp_null_and_invalid_arguments(lib):
+    L = lib._lib
+    h = ctypes.c_void_p()
+    fp = ctypes.POINTER(ctypes.c_float)
+    init = (ctypes.c_float * lib.MLP_NPARAM)()
+    six = (ctypes.c_float * 6)(*([1.0] * 6))
+    assert L.psatd_mlp_create(None, six, six, 0.0, 1.0, 16, ctypes.byref(h)) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_create(ctypes.cast(init, fp), six, six, 0.0, 1.0, 16, None) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_create(ctypes.cast(init, fp), six, six, 0.0, 1.0, 0, ctypes.byref(h)) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_create(ctypes.cast(init, fp), six, six, 0.0, 0.0, 16, ctypes.byref(h)) == lib.PSATD_EINVAL
+    assert h.value is None
+    assert L.psatd_mlp_set(None, None) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_get(None, None, None) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_predict(None, None, 4, None, None) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_grad(None, None, None, 4, None, 4, None, None, None) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == lib.PSATD_EINVAL
+    assert L.psatd_mlp_train(None, None, None, 4, None, 1, 4, 1e-3, 0.9, 0.999, 1e-8, None, None) == lib.PSATD_EINVAL
+    L.psatd_mlp_destroy(None)  # NULL-safe
+    assert "psatd_mlp" in L.psatd_last_error().decode()
