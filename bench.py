@@ -145,8 +145,8 @@ def run_gpu(precision, inputs_host, steps, warmup):
     return res, fields
 
 
-def cpu_baseline():
-    """The FP64 oracle on a half-scale copy of the workload: one local step of a
+def cpu_baseline(nsteps=4):
+    """The FP64 oracle on a half-scale copy of the workload: ``nsteps`` local steps of a
     256 x 128 x 128 grid with 16 guards (box 288 x 160 x 160, same box/interior ratio)."""
     import oracle.step
     from oracle import domain
@@ -155,12 +155,12 @@ def cpu_baseline():
     g1 = make_inputs(interior, DX, DT, seed_stream=7)
     box = {"origin": (0, 0, 0), "interior": interior, "nguard": 16, "order": ORDER}
     t0 = time.perf_counter()
-    domain.local_step(g1, [box], DX, DT)
+    domain.local_steps(g1, [box], nsteps, DX, DT)
     t = time.perf_counter() - t0
-    cells = interior[0] * interior[1] * interior[2]
+    cells = interior[0] * interior[1] * interior[2] * nsteps
     return {"value": cells / t, "unit": "cell-updates/s", "cores": oracle.step.WORKERS, "kind": "oracle",
-            "sample": f"1 FP64 step of the oracle (complex FFTs, order 100) on a 256x128x128 grid + 16 guards "
-                      f"(box 288x160x160, same box/interior ratio as the workload), {t:.1f} s"}
+            "sample": f"{nsteps} FP64 steps of the oracle (complex FFTs, order 100) on a 256x128x128 grid + 16 "
+                      f"guards (box 288x160x160, same box/interior ratio as the workload), {t:.1f} s"}
 
 
 def run_batch(steps):
@@ -204,6 +204,60 @@ def run_batch(steps):
             "ms_per_step_graph": t_graph * 1e3, "ms_per_step_eager": t_eager * 1e3}
 
 
+def summarize_pmc(directory, steps, out_json):
+    """HBM traffic per launch of each pass from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this script.
+
+    Both counters are in KiB per dispatch.  They are calibrated by the 1 GiB
+    read + 1 GiB write of the --calibration-copy kernel (torch.neg) in the same
+    runs; only the last ``steps`` dispatches of each pass kernel (the timed
+    steps, after autotuning and warm-up) are averaged.
+    """
+    import csv
+    import glob
+
+    names = {"k_xfwd<": "x_fwd_fill", "k_ypass<-1": "y_fwd", "k_zpush<": "z_push", "k_ypass<1": "y_inv",
+             "k_xinv<": "x_inv_merge"}
+    per = {"FETCH_SIZE": {}, "WRITE_SIZE": {}}
+    calib = {}
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                c = r["Counter_Name"]
+                if c not in per:
+                    continue
+                k = r["Kernel_Name"]
+                v = float(r["Counter_Value"])
+                if "neg_kernel" in k:
+                    calib[c] = v
+                    continue
+                for key, pas in names.items():
+                    if key in k and "_b<" not in k and "k_xfwd_b" not in k:
+                        per[c].setdefault(pas, []).append((int(r["Dispatch_Id"]), v))
+    if set(calib) != {"FETCH_SIZE", "WRITE_SIZE"}:
+        raise SystemExit("calibration kernel (neg) not found in both counter runs")
+    gib_kib = float(1 << 20)
+    factor = {c: gib_kib / calib[c] for c in calib}
+    alg = algorithmic_bytes(tuple(n + 2 * NGUARD for n in INTERIOR), INTERIOR, NGUARD, 4)
+    passes = {}
+    for pas in PASSES:
+        vals = {}
+        for c in per:
+            d = sorted(per[c].get(pas, []))[-steps:]
+            vals[c] = sum(v for _, v in d) / len(d) if d else float("nan")
+        b = 1024.0 * (vals["FETCH_SIZE"] * factor["FETCH_SIZE"] + vals["WRITE_SIZE"] * factor["WRITE_SIZE"])
+        passes[pas] = {"fetch_kib": vals["FETCH_SIZE"], "write_kib": vals["WRITE_SIZE"],
+                       "bytes_per_launch": round(b), "algorithmic_bytes": alg[pas], "ratio": round(b / alg[pas], 4)}
+    rec = {"source_digest": source_digest(), "workload": "512x256x256 + 32 guards, order 100, FP32",
+           "calibration": {"kernel": "torch.neg over 1 GiB (reads 1 GiB, writes 1 GiB)",
+                           "fetch_kib": calib["FETCH_SIZE"], "write_kib": calib["WRITE_SIZE"],
+                           "fetch_factor": round(factor["FETCH_SIZE"], 4),
+                           "write_factor": round(factor["WRITE_SIZE"], 4)},
+           "passes": passes}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,7 +268,13 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="write profiles/hbm_traffic_config2_fp32.json from rocprofv3 --pmc runs under DIR and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.steps,
+                      os.path.join(ROOT, "profiles", "hbm_traffic_config2_fp32.json"))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the PSATD step of one group runs on a single MI355X "
               "(multi-GPU groups are not part of this build); use --gpus 1", file=sys.stderr)
@@ -231,11 +291,12 @@ def main():
     interior_cells = nx * ny * nz
 
     if args.calibration_copy:
-        # A plain 1 GiB device-to-device copy: under a counter profiler its
-        # FETCH_SIZE / WRITE_SIZE calibrate the counters against known bytes.
+        # A plain streaming kernel that reads 1 GiB and writes 1 GiB (b = -a):
+        # under a counter profiler its FETCH_SIZE / WRITE_SIZE calibrate the
+        # counters against known bytes.
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
         log("calibration copy of 1 GiB done")

@@ -111,6 +111,8 @@ struct XInvParams {
 
 // Threads per block of each pass and register budgets of the tile prefetch.
 constexpr int kLineThreads = 512;
+// Block sizes of the z pass (tried in this order; the first whose 11 lines fit is used).
+constexpr int kZThreads[3] = {256, 512, 1024};
 template <typename T>
 struct prefetch_budget;  // complex values per thread held for the next tile
 template <>
@@ -154,7 +156,6 @@ template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s);
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s);
-int zpush_points_per_thread();
 
 // Tables (FP64 math, stored at working precision).
 void launch_twiddles(void* dst, int n, int fp64, hipStream_t s);

@@ -314,73 +314,50 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
 // Push (Sec. 1.1; J constant over the step, rho at both ends):
 //   E' = C E + i c^2 S1 (K x B) - (S1/eps0) J + i (c^2/eps0) K (X3 rho_old - X2 rho_new)
 //   B' = C B - i S1 (K x E) + i (X1/eps0) (K x J)
+// A tile is one (kx, ky) column: its 11 z-lines are loaded into LDS,
+// transformed, pushed point by point, and the 6 lines of E and B transformed
+// back and stored over the interior z range.  Unlike the other passes this one
+// does not hold the next tile in registers: the transforms of 17 lines leave
+// no room for it, and small blocks with a 128-register cap (FP32) let several
+// columns per CU overlap each other's loads and barriers instead.
 // Each wave moves whole z-lines (lines w, w + nwaves, ...), so the field of a
 // wave's load is uniform and one buffer resource serves it.
-constexpr int kZPts = 2;  // k-space points per thread in the push (NZ <= kZPts * threads)
-
 template <typename T, typename Src>
 __device__ __forceinline__ void zpush_body(const Src& S) {
-  constexpr int PF = prefetch_budget<T>::v;
+  constexpr int kRound = 16;  // line chunks of 64 points loaded per thread before they go to LDS
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63;
   const int wave = uniform(tid >> 6);
   const int nwaves = nth >> 6;
-  cx<T> r[PF];
-  T cc[kZPts][5];
-
-  // slot u of the prefetch = (this wave's line number s, chunk i): line wave + s*nwaves, z = lane + 64 i
-  auto issue = [&](int tile) {
-    int col;
-    const ZPushParams<T>& p = S.box(tile, col);
-    const int NZ = p.NZ;
-    const int per_line = (NZ + 63) >> 6;
-    int s = 0, i = 0;
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int l = wave + s * nwaves;
-      const rsrc_t rb = make_rsrc(p.b + (i64)(l < 11 ? l : 0) * p.npts, p.field_bytes);
-      const int z = lane + 64 * i;
-      const uint32_t idx = (l < 11 && z < NZ) ? (uint32_t)(col * NZ + z) : kOOB;
-      r[u] = gm<T>::ldc(rb, idx);
-      if (++i == per_line) {
-        i = 0;
-        ++s;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kZPts; ++q) {
-      const int kz = tid + q * nth;
-      const uint32_t idx = kz < NZ ? (uint32_t)(col * NZ + kz) : kOOB;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) cc[q][c] = gm<T>::ld(make_rsrc(p.coef + (i64)c * p.npts, p.coef_bytes), idx);
-    }
-  };
-
-  int tile = blockIdx.x;
-  if (tile >= S.ntiles()) return;
-  issue(tile);
-  for (;;) {
+  for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
     int col;
     const ZPushParams<T>& p = S.box(tile, col);
     const int NZ = p.NZ;
     const int ld = fft_slots(p.fft.sch.n);
-    {
-      const int per_line = (NZ + 63) >> 6;
-      int s = 0, i = 0;
+    const int per_line = (NZ + 63) >> 6;
+    const int items = ((11 - wave + nwaves - 1) / nwaves) * per_line;  // (line, chunk) pairs of this wave
+    for (int q0 = 0; q0 < items; q0 += kRound) {
+      cx<T> r[kRound];
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const int l = wave + s * nwaves;
+      for (int u = 0; u < kRound; ++u) {
+        const int q = q0 + u;
+        const int sl = q / per_line, i = q - sl * per_line;
+        const int l = wave + sl * nwaves;
         const int z = lane + 64 * i;
-        if (l < 11 && z < NZ) lds[l * ld + lpad(z)] = r[u];
-        if (++i == per_line) {
-          i = 0;
-          ++s;
-        }
+        const bool ok = q < items && z < NZ;
+        const rsrc_t rb = make_rsrc(p.b + (i64)(ok ? l : 0) * p.npts, p.field_bytes);
+        r[u] = gm<T>::ldc(rb, ok ? (uint32_t)(col * NZ + z) : kOOB);
+      }
+#pragma unroll
+      for (int u = 0; u < kRound; ++u) {
+        const int q = q0 + u;
+        const int sl = q / per_line, i = q - sl * per_line;
+        const int z = lane + 64 * i;
+        if (q < items && z < NZ) lds[(wave + sl * nwaves) * ld + lpad(z)] = r[u];
       }
     }
     __syncthreads();
-    const int next = tile + gridDim.x;
     lds_line_fft<-1, T>(lds, ld, 11, p.fft);
 
     const int kxi = fdiv(col, p.fd_NY);
@@ -388,11 +365,12 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
     const T kx = p.kx[kxi];
     const T ky = p.ky[kyi];
     const T c2 = p.c2, ie = p.inv_eps0;
+    for (int kz = tid; kz < NZ; kz += nth) {
+      const uint32_t idx = (uint32_t)(col * NZ + kz);
+      T cc[5];
 #pragma unroll
-    for (int q = 0; q < kZPts; ++q) {
-      const int kz = tid + q * nth;
-      if (kz >= NZ) continue;
-      const T C = cc[q][0], S1 = cc[q][1], X1 = cc[q][2], X2 = cc[q][3], X3 = cc[q][4];
+      for (int c = 0; c < 5; ++c) cc[c] = gm<T>::ld(make_rsrc(p.coef + (i64)c * p.npts, p.coef_bytes), idx);
+      const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
       const T kzz = p.kz[kz];
       const int s = lpad(kz);
       const cx<T> ex = lds[0 * ld + s], ey = lds[1 * ld + s], ez = lds[2 * ld + s];
@@ -429,9 +407,6 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
       lds[4 * ld + s] = {C * by.re - wy.im, C * by.im + wy.re};
       lds[5 * ld + s] = {C * bz.re - wz.im, C * bz.im + wz.re};
     }
-    // The next column's loads fly during the inverse transform and the stores
-    // (issued here rather than before the push to keep the push's registers free).
-    if (next < S.ntiles()) issue(next);
     __syncthreads();
     lds_line_fft<1, T>(lds, ld, 6, p.fft);
 
@@ -440,8 +415,6 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
       for (int z = p.z_lo + lane; z < p.z_hi; z += 64) gm<T>::stc(rb, (uint32_t)(col * NZ + z), lds[l * ld + lpad(z)]);
     }
     __syncthreads();
-    if (next >= S.ntiles()) break;
-    tile = next;
   }
 }
 
@@ -570,12 +543,15 @@ template <int S, typename T>
 __global__ void __launch_bounds__(kLineThreads) k_ypass_b(BatchArgs<YPassParams<T>> a) {
   ypass_body<S, T>(BatchSrc<YPassParams<T>>{a});
 }
+// z pass: at most 128 registers in FP32 (4 waves per SIMD), 256 in FP64 (2).
 template <typename T, int NTH>
-__global__ void __launch_bounds__(NTH) k_zpush(ZPushParams<T>) {
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+k_zpush(ZPushParams<T>) {
   zpush_body<T>(SingleSrc<ZPushParams<T>>{});
 }
 template <typename T, int NTH>
-__global__ void __launch_bounds__(NTH) k_zpush_b(BatchArgs<ZPushParams<T>> a) {
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+k_zpush_b(BatchArgs<ZPushParams<T>> a) {
   zpush_body<T>(BatchSrc<ZPushParams<T>>{a});
 }
 // FP32: capping the registers at 128 (two blocks per CU) is faster for this
@@ -663,10 +639,12 @@ void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
 }
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
-  if (nthreads == kLineThreads)
-    launch_persistent(k_zpush<T, kLineThreads>, p, nthreads, zpush_lds(p), p.ntiles, s);
+  if (nthreads == kZThreads[0])
+    launch_persistent(k_zpush<T, kZThreads[0]>, p, nthreads, zpush_lds(p), p.ntiles, s);
+  else if (nthreads == kZThreads[1])
+    launch_persistent(k_zpush<T, kZThreads[1]>, p, nthreads, zpush_lds(p), p.ntiles, s);
   else
-    launch_persistent(k_zpush<T, 2 * kLineThreads>, p, nthreads, zpush_lds(p), p.ntiles, s);
+    launch_persistent(k_zpush<T, kZThreads[2]>, p, nthreads, zpush_lds(p), p.ntiles, s);
 }
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
@@ -686,17 +664,18 @@ void launch_ypass_batch(const BatchArgs<YPassParams<T>>& a, int inverse, size_t 
 }
 template <typename T>
 void launch_zpush_batch(const BatchArgs<ZPushParams<T>>& a, int nthreads, size_t lds, hipStream_t s) {
-  if (nthreads == kLineThreads)
-    launch_persistent(k_zpush_b<T, kLineThreads>, a, nthreads, lds, a.total, s);
+  if (nthreads == kZThreads[0])
+    launch_persistent(k_zpush_b<T, kZThreads[0]>, a, nthreads, lds, a.total, s);
+  else if (nthreads == kZThreads[1])
+    launch_persistent(k_zpush_b<T, kZThreads[1]>, a, nthreads, lds, a.total, s);
   else
-    launch_persistent(k_zpush_b<T, 2 * kLineThreads>, a, nthreads, lds, a.total, s);
+    launch_persistent(k_zpush_b<T, kZThreads[2]>, a, nthreads, lds, a.total, s);
 }
 template <typename T>
 void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_t s) {
   launch_persistent(k_xinv_b<T>, a, kLineThreads, lds, a.total, s);
 }
 
-int zpush_points_per_thread() { return kZPts; }
 
 #define PSATD_INSTANTIATE(T)                                                                      \
   template void launch_xfwd<T>(const XFwdParams<T>&, hipStream_t);                                \

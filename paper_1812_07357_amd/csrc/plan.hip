@@ -256,10 +256,8 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   p->ty5 = 2 * std::max(nc5, 0);
   p->nl_y = std::min(fit_lines(sys, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
   p->zthreads = 0;
-  for (int zt : {nth, 2 * nth}) {
-    const int lines_per_wave = (11 + zt / 64 - 1) / (zt / 64);
-    if (p->NZ <= zpush_points_per_thread() * zt && lines_per_wave * ((p->NZ + 63) / 64) <= pf &&
-        fit_lines(szs, zt, em, cs, 11, lds_limit()) == 11) {
+  for (int zt : kZThreads) {
+    if (fit_lines(szs, zt, em, cs, 11, lds_limit()) == 11) {
       p->zthreads = zt;
       break;
     }
@@ -754,11 +752,8 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
         const int hi = std::min(fit_lines(A.sch, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
         for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(t);
       } else {
-        for (int zt : {nth, 2 * nth})
-          if (p->NZ <= zpush_points_per_thread() * zt &&
-              ((11 + zt / 64 - 1) / (zt / 64)) * ((p->NZ + 63) / 64) <= pf &&
-              fit_lines(A.sch, zt, em, cs, 11, lds_limit()) == 11)
-            tl.push_back(zt);
+        for (int zt : kZThreads)
+          if (fit_lines(A.sch, zt, em, cs, 11, lds_limit()) == 11 && tl.size() < 2) tl.push_back(zt);
       }
       if (hit != tune_cache().end()) tl = {hit->second.tile};
       for (int t : tl) {

@@ -215,11 +215,19 @@ class Model:
     metrics: dict
 
 
+# Labels above this are capped: an error as large as the field itself means the
+# run is unusable (at infinite order and large c dt/dx the local solve can even
+# grow without bound), and how far beyond that it goes does not matter for the
+# choice of n_g.
+LABEL_CAP = 0.0
+
+
 def train(X: np.ndarray, y: np.ndarray, run_ids: np.ndarray, rng: np.random.Generator, steps: int = 4000,
           batch: int = 512, lr: float = 1e-3, quantile: float = 0.95):
     """Fit the network on the training runs; the margin is the ``quantile`` of held-out under-predictions."""
     import torch
 
+    y = np.minimum(np.asarray(y, dtype=np.float32), np.float32(LABEL_CAP))
     tr, va, te = split_runs(run_ids, rng)
     mean = X[tr].mean(axis=0)
     std = X[tr].std(axis=0)
