@@ -83,77 +83,62 @@ struct BatchSrc {
 };
 
 // ------------------------------------------------------------------ P1
+// Tiles are ty consecutive y rows of one (field, z) plane, packed as ty/2
+// complex lines.  Loads go straight to LDS (in rounds that keep up to one
+// prefetch budget of values in flight per thread); overlap comes from several
+// blocks per CU.
 template <typename T, typename Src>
 __device__ __forceinline__ void xfwd_body(const Src& S) {
-  constexpr int PF = prefetch_budget<T>::v;
+  constexpr int kRound = prefetch_budget<T>::v;  // element pairs loaded per thread before they go to LDS
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
-  T re[PF], im[PF];
 
-  auto decode = [&](const XFwdParams<T>& p, int lt, int& f, int& z, int& ybase) {
+  for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
+    int lt;
+    const XFwdParams<T>& p = S.box(tile, lt);
     const int q = fdiv(lt, p.fd_ytiles);
-    ybase = (lt - q * p.ytiles) * p.ty;
-    f = fdiv(q, p.fd_NZ);
-    z = q - f * p.NZ;
-  };
-  auto issue = [&](int tile) {
-    int lt;
-    const XFwdParams<T>& p = S.box(tile, lt);
-    int f, z, ybase;
-    decode(p, lt, f, z, ybase);
-    const int NX = p.NX, NY = p.NY;
-    const int nld = (p.ty >> 1) * NX;
-    const rsrc_t src = make_rsrc(p.src[f], p.src_bytes);
-    const int zrow = p.gather ? fmod_i(p.z0 + z, p.fd_GZ) * p.GY : z * NY;
-    const int rowlen = p.gather ? p.GX : NX;
-    Walk w;
-    w.row = fdiv(tid, p.fd_NX);
-    w.col = tid - w.row * NX;
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + u * nth;
-      uint32_t ia = kOOB, ib = kOOB;
-      if (e < nld) {
-        const int ya = ybase + 2 * w.row;
-        int xs = w.col, ra = ya, rb = ya + 1;
-        if (p.gather) {
-          xs = fmod_i(p.x0 + w.col, p.fd_GX);
-          ra = fmod_i(p.y0 + ya, p.fd_GY);
-          rb = fmod_i(p.y0 + ya + 1, p.fd_GY);
-        }
-        if (ya < NY) ia = (uint32_t)((zrow + ra) * rowlen + xs);
-        if (ya + 1 < NY) ib = (uint32_t)((zrow + rb) * rowlen + xs);
-      }
-      re[u] = gm<T>::ld(src, ia);
-      im[u] = gm<T>::ld(src, ib);
-      w.next(p.ld_drow, p.ld_dcol, NX);
-    }
-  };
-
-  int tile = blockIdx.x;
-  if (tile >= S.ntiles()) return;
-  issue(tile);
-  for (;;) {
-    int lt;
-    const XFwdParams<T>& p = S.box(tile, lt);
-    int f, z, ybase;
-    decode(p, lt, f, z, ybase);
+    const int ybase = (lt - q * p.ytiles) * p.ty;
+    const int f = fdiv(q, p.fd_NZ);
+    const int z = q - f * p.NZ;
     const int NX = p.NX, NY = p.NY, NXH = p.NXH, ty = p.ty, nc = ty >> 1;
     const int ld = fft_slots(p.fft.sch.n);
+    const int nld = nc * NX;
     {
-      const int nld = nc * NX;
+      const rsrc_t src = make_rsrc(p.src[f], p.src_bytes);
+      const int zrow = p.gather ? fmod_i(p.z0 + z, p.fd_GZ) * p.GY : z * NY;
+      const int rowlen = p.gather ? p.GX : NX;
       Walk w;
       w.row = fdiv(tid, p.fd_NX);
       w.col = tid - w.row * NX;
+      for (int e0 = 0; e0 < nld; e0 += kRound * nth) {
+        T re[kRound], im[kRound];
+        Walk w0 = w;
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        if (tid + u * nth < nld) lds[w.row * ld + lpad(w.col)] = {re[u], im[u]};
-        w.next(p.ld_drow, p.ld_dcol, NX);
+        for (int u = 0; u < kRound; ++u) {
+          uint32_t ia = kOOB, ib = kOOB;
+          if (e0 + tid + u * nth < nld) {
+            const int ya = ybase + 2 * w.row;
+            int xs = w.col, ra = ya, rb = ya + 1;
+            if (p.gather) {
+              xs = fmod_i(p.x0 + w.col, p.fd_GX);
+              ra = fmod_i(p.y0 + ya, p.fd_GY);
+              rb = fmod_i(p.y0 + ya + 1, p.fd_GY);
+            }
+            if (ya < NY) ia = (uint32_t)((zrow + ra) * rowlen + xs);
+            if (ya + 1 < NY) ib = (uint32_t)((zrow + rb) * rowlen + xs);
+          }
+          re[u] = gm<T>::ld(src, ia);
+          im[u] = gm<T>::ld(src, ib);
+          w.next(p.ld_drow, p.ld_dcol, NX);
+        }
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+          if (e0 + tid + u * nth < nld) lds[w0.row * ld + lpad(w0.col)] = {re[u], im[u]};
+          w0.next(p.ld_drow, p.ld_dcol, NX);
+        }
       }
     }
     __syncthreads();
-    const int next = tile + gridDim.x;
-    if (next < S.ntiles()) issue(next);
     lds_line_fft<-1, T>(lds, ld, nc, p.fft);
 
     // Split each complex line into the half spectra of its two real lines; y fastest.
@@ -181,8 +166,6 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
       v.next(p.wr_drow, p.wr_dcol, ty);
     }
     __syncthreads();
-    if (next >= S.ntiles()) break;
-    tile = next;
   }
 }
 
@@ -527,12 +510,15 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
 }
 
 // ------------------------------------------------------------------ kernels
+// x forward: at most 128 registers in FP32 (two blocks per CU).
 template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xfwd(XFwdParams<T>) {
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_xfwd(XFwdParams<T>) {
   xfwd_body<T>(SingleSrc<XFwdParams<T>>{});
 }
 template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xfwd_b(BatchArgs<XFwdParams<T>> a) {
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_xfwd_b(BatchArgs<XFwdParams<T>> a) {
   xfwd_body<T>(BatchSrc<XFwdParams<T>>{a});
 }
 template <int S, typename T>
