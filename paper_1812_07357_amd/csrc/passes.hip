@@ -170,12 +170,13 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
 }
 
 // ------------------------------------------------------------------ P2 / P4
+// Tiles are up to 16 y-lines; loads go straight to LDS in rounds of one
+// prefetch budget per thread, and several blocks per CU overlap each other.
 template <int S_, typename T, typename Src>
 __device__ __forceinline__ void ypass_body(const Src& S) {
-  constexpr int PF = prefetch_budget<T>::v;
+  constexpr int kRound = prefetch_budget<T>::v;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
-  cx<T> r[PF];
 
   struct Tile {
     int f, o, u0, nlt;
@@ -210,55 +211,44 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
       ncol = t.nlt;
     }
   };
-  auto issue = [&](int tile) {
-    int lt;
-    const YPassParams<T>& p = S.box(tile, lt);
-    const Tile t = decode(p, lt);
-    const rsrc_t in = make_rsrc(p.in + (i64)t.f * p.fs_in, p.in_bytes);
-    const int base = t.o * p.os_in + t.u0 * p.ls_in;
-    const int tot = t.nlt * p.n;
-    Walk w;
-    int dr, dc, ncol;
-    start_in(p, t, w, dr, dc, ncol);
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      uint32_t idx = kOOB;
-      if (tid + u * nth < tot) {
-        const int li = (p.ps_in == 1) ? w.row : w.col;
-        const int q = (p.ps_in == 1) ? w.col : w.row;
-        idx = (uint32_t)(base + li * p.ls_in + q * p.ps_in);
-      }
-      r[u] = gm<T>::ldc(in, idx);
-      w.next(dr, dc, ncol);
-    }
-  };
-
-  int tile = blockIdx.x;
-  if (tile >= S.ntiles()) return;
-  issue(tile);
-  for (;;) {
+  for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
     int lt;
     const YPassParams<T>& p = S.box(tile, lt);
     const Tile t = decode(p, lt);
     const int ld = fft_slots(p.fft.sch.n);
     {
+      const rsrc_t in = make_rsrc(p.in + (i64)t.f * p.fs_in, p.in_bytes);
+      const int base = t.o * p.os_in + t.u0 * p.ls_in;
+      const int tot = t.nlt * p.n;
       Walk w;
       int dr, dc, ncol;
       start_in(p, t, w, dr, dc, ncol);
-      const int tot = t.nlt * p.n;
+      for (int e0 = 0; e0 < tot; e0 += kRound * nth) {
+        cx<T> r[kRound];
+        Walk w0 = w;
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        if (tid + u * nth < tot) {
-          const int li = (p.ps_in == 1) ? w.row : w.col;
-          const int q = (p.ps_in == 1) ? w.col : w.row;
-          lds[li * ld + lpad(q)] = r[u];
+        for (int u = 0; u < kRound; ++u) {
+          uint32_t idx = kOOB;
+          if (e0 + tid + u * nth < tot) {
+            const int li = (p.ps_in == 1) ? w.row : w.col;
+            const int q = (p.ps_in == 1) ? w.col : w.row;
+            idx = (uint32_t)(base + li * p.ls_in + q * p.ps_in);
+          }
+          r[u] = gm<T>::ldc(in, idx);
+          w.next(dr, dc, ncol);
         }
-        w.next(dr, dc, ncol);
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+          if (e0 + tid + u * nth < tot) {
+            const int li = (p.ps_in == 1) ? w0.row : w0.col;
+            const int q = (p.ps_in == 1) ? w0.col : w0.row;
+            lds[li * ld + lpad(q)] = r[u];
+          }
+          w0.next(dr, dc, ncol);
+        }
       }
     }
     __syncthreads();
-    const int next = tile + gridDim.x;
-    if (next < S.ntiles()) issue(next);
     lds_line_fft<S_, T>(lds, ld, t.nlt, p.fft);
 
     const rsrc_t out = make_rsrc(p.out + (i64)t.f * p.fs_out, p.out_bytes);
@@ -288,8 +278,6 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
       w.next(dr, dc, ncol);
     }
     __syncthreads();
-    if (next >= S.ntiles()) break;
-    tile = next;
   }
 }
 
@@ -402,80 +390,64 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
 }
 
 // ------------------------------------------------------------------ P5
+// Tiles are ty/2 complex x-lines rebuilt from the half spectra of ty real
+// lines; loads go straight to LDS in rounds, several blocks per CU overlap.
 template <typename T, typename Src>
 __device__ __forceinline__ void xinv_body(const Src& S) {
-  constexpr int PF2 = prefetch_budget<T>::v / 2;  // two values per element
+  constexpr int kRound = prefetch_budget<T>::v / 2;  // two values per element
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
-  cx<T> a[PF2], b[PF2];
 
-  auto decode = [&](const XInvParams<T>& p, int lt, int& f, int& z, int& ybase) {
+  for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
+    int lt;
+    const XInvParams<T>& p = S.box(tile, lt);
     const int q = fdiv(lt, p.fd_ytiles);
-    ybase = p.y_lo + (lt - q * p.ytiles) * p.ty;
-    f = fdiv(q, p.fd_nz);
-    z = p.z_lo + (q - f * (p.z_hi - p.z_lo));
-  };
-  auto issue = [&](int tile) {
-    int lt;
-    const XInvParams<T>& p = S.box(tile, lt);
-    int f, z, ybase;
-    decode(p, lt, f, z, ybase);
-    const int NXH = p.NXH, NY = p.NY, nc = p.ty >> 1;
-    const int nld = nc * NXH;
-    const rsrc_t src = make_rsrc(p.src + (i64)f * p.npts, p.src_bytes);
-    const int sbase = z * NXH * NY;
-    Walk w;
-    w.row = fdiv(tid, p.fd_nc);  // (kx, complex line)
-    w.col = tid - w.row * nc;
-#pragma unroll
-    for (int u = 0; u < PF2; ++u) {
-      uint32_t ia = kOOB, ib = kOOB;
-      if (tid + u * nth < nld) {
-        const int ya = ybase + 2 * w.col;
-        if (ya < p.y_hi) ia = (uint32_t)(sbase + w.row * NY + ya);
-        if (ya + 1 < p.y_hi) ib = (uint32_t)(sbase + w.row * NY + ya + 1);
-      }
-      a[u] = gm<T>::ldc(src, ia);
-      b[u] = gm<T>::ldc(src, ib);
-      w.next(p.ld_drow, p.ld_dcol, nc);
-    }
-  };
-
-  int tile = blockIdx.x;
-  if (tile >= S.ntiles()) return;
-  issue(tile);
-  for (;;) {
-    int lt;
-    const XInvParams<T>& p = S.box(tile, lt);
-    int f, z, ybase;
-    decode(p, lt, f, z, ybase);
-    const int NX = p.NX, NY = p.NY, nc = p.ty >> 1;
+    const int ybase = p.y_lo + (lt - q * p.ytiles) * p.ty;
+    const int f = fdiv(q, p.fd_nz);
+    const int z = p.z_lo + (q - f * (p.z_hi - p.z_lo));
+    const int NX = p.NX, NY = p.NY, NXH = p.NXH, nc = p.ty >> 1;
     const int ld = fft_slots(p.fft.sch.n);
     {
       // Rebuild Z = A + i B over the full line from the half spectra of the two real lines.
-      const int nld = nc * p.NXH;
+      const int nld = nc * NXH;
+      const rsrc_t src = make_rsrc(p.src + (i64)f * p.npts, p.src_bytes);
+      const int sbase = z * NXH * NY;
       Walk w;
-      w.row = fdiv(tid, p.fd_nc);
+      w.row = fdiv(tid, p.fd_nc);  // (kx, complex line)
       w.col = tid - w.row * nc;
+      for (int e0 = 0; e0 < nld; e0 += kRound * nth) {
+        cx<T> av[kRound], bv[kRound];
+        Walk w0 = w;
 #pragma unroll
-      for (int u = 0; u < PF2; ++u) {
-        if (tid + u * nth < nld) {
-          const int kx = w.row, c = w.col;
-          cx<T> av = a[u], bv = b[u];
-          const bool selfconj = (kx == 0) || (2 * kx == NX);
-          if (selfconj) {
-            av.im = T(0);
-            bv.im = T(0);
+        for (int u = 0; u < kRound; ++u) {
+          uint32_t ia = kOOB, ib = kOOB;
+          if (e0 + tid + u * nth < nld) {
+            const int ya = ybase + 2 * w.col;
+            if (ya < p.y_hi) ia = (uint32_t)(sbase + w.row * NY + ya);
+            if (ya + 1 < p.y_hi) ib = (uint32_t)(sbase + w.row * NY + ya + 1);
           }
-          lds[c * ld + lpad(kx)] = {av.re - bv.im, av.im + bv.re};
-          if (!selfconj) lds[c * ld + lpad(NX - kx)] = {av.re + bv.im, bv.re - av.im};
+          av[u] = gm<T>::ldc(src, ia);
+          bv[u] = gm<T>::ldc(src, ib);
+          w.next(p.ld_drow, p.ld_dcol, nc);
         }
-        w.next(p.ld_drow, p.ld_dcol, nc);
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+          if (e0 + tid + u * nth < nld) {
+            const int kx = w0.row, c = w0.col;
+            cx<T> x = av[u], y = bv[u];
+            const bool selfconj = (kx == 0) || (2 * kx == NX);
+            if (selfconj) {
+              x.im = T(0);
+              y.im = T(0);
+            }
+            lds[c * ld + lpad(kx)] = {x.re - y.im, x.im + y.re};
+            if (!selfconj) lds[c * ld + lpad(NX - kx)] = {x.re + y.im, y.re - x.im};
+          }
+          w0.next(p.ld_drow, p.ld_dcol, nc);
+        }
       }
     }
     __syncthreads();
-    const int next = tile + gridDim.x;
-    if (next < S.ntiles()) issue(next);
     lds_line_fft<1, T>(lds, ld, nc, p.fft);
 
     const rsrc_t dst = make_rsrc(p.dst[f], p.dst_bytes);
@@ -504,8 +476,6 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
       v.next(p.wr_drow, p.wr_dcol, NX);
     }
     __syncthreads();
-    if (next >= S.ntiles()) break;
-    tile = next;
   }
 }
 
@@ -522,11 +492,13 @@ k_xfwd_b(BatchArgs<XFwdParams<T>> a) {
   xfwd_body<T>(BatchSrc<XFwdParams<T>>{a});
 }
 template <int S, typename T>
-__global__ void __launch_bounds__(kLineThreads) k_ypass(YPassParams<T>) {
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_ypass(YPassParams<T>) {
   ypass_body<S, T>(SingleSrc<YPassParams<T>>{});
 }
 template <int S, typename T>
-__global__ void __launch_bounds__(kLineThreads) k_ypass_b(BatchArgs<YPassParams<T>> a) {
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_ypass_b(BatchArgs<YPassParams<T>> a) {
   ypass_body<S, T>(BatchSrc<YPassParams<T>>{a});
 }
 // z pass: at most 128 registers in FP32 (4 waves per SIMD), 256 in FP64 (2).
@@ -540,15 +512,15 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof
 k_zpush_b(BatchArgs<ZPushParams<T>> a) {
   zpush_body<T>(BatchSrc<ZPushParams<T>>{a});
 }
-// FP32: capping the registers at 128 (two blocks per CU) is faster for this
-// pass despite a few bytes of spill; the other passes lose more than they gain.
+// x inverse: at most 128 registers in FP32 (two blocks per CU).
 template <typename T>
 __global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 k_xinv(XInvParams<T>) {
   xinv_body<T>(SingleSrc<XInvParams<T>>{});
 }
 template <typename T>
-__global__ void __launch_bounds__(kLineThreads) k_xinv_b(BatchArgs<XInvParams<T>> a) {
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_xinv_b(BatchArgs<XInvParams<T>> a) {
   xinv_body<T>(BatchSrc<XInvParams<T>>{a});
 }
 
