@@ -11,6 +11,12 @@
 // stage runs in place: every thread first reads all of its butterflies into
 // registers, the block synchronises, then every thread writes.
 //
+// Twiddle table layout (stage-major): the R-1 twiddles of butterfly k of the
+// stage with span Ns are consecutive, at tw[(Ns - 1) + k (R - 1) + (t - 1)]
+// = w_n^(t k n/(Ns R)) for t = 1..R-1.  The stages' blocks telescope to
+// n - 1 entries in all, and a butterfly reads its twiddles from one base
+// address at fixed offsets.
+//
 // Element i of a line lives at LDS slot i + i/16 of that line: the first stage
 // writes with a stride of R elements, and without the padding slot every
 // lane of a 16-lane group would hit the same LDS bank for R = 16.
@@ -56,7 +62,11 @@ struct emax<float> { static constexpr int v = 17; };
 template <>
 struct emax<double> { static constexpr int v = 17; };
 
-__host__ __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// i + floor(i / 16) == floor(17 i / 16) for 0 <= i < 2^27: one multiply-shift, and a
+// sequence i0 + t d becomes a running sum of 17 d.
+__host__ __device__ __forceinline__ int lpad(int i) { return (int)((17u * (uint32_t)i) >> 4); }
+// floor(q / 16): with q = 17 i + 16 base this is base + lpad(i).
+__device__ __forceinline__ int pad_slot(uint32_t q) { return (int)(q >> 4); }
 // LDS slots per line of n elements (odd, so that lanes walking across lines use distinct banks).
 __host__ __device__ __forceinline__ int lds_line(int n) { return (lpad(n - 1) + 1) | 1; }
 
@@ -69,7 +79,7 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, i
   const int total = nlines * bfl;
   const int nth = blockDim.x;
   const int tid = threadIdx.x;
-  const int twstep = n / (Ns * R);
+  const uint32_t dq_in = 17u * (uint32_t)bfl, dq_out = 17u * (uint32_t)Ns;
   cx<T> v[MB][R];
   int lbase[MB];  // LDS offset of the butterfly's line, -1 if none
   int obase[MB];  // first output position (jj - k) R + k within the line
@@ -82,12 +92,18 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, i
       const int line = fdiv(j, fb);
       const int jj = j - line * bfl;
       const int k = jj - fdiv(jj, fn) * Ns;
-      const cx<T>* src = lds + line * ld;
+      // slot of element jj + t bfl of the line: line * ld + floor(q / 16) with
+      // q = 17 (jj + t bfl) kept as a running sum (the line offset folded in as 16 line * ld)
+      uint32_t q = 17u * (uint32_t)jj + 16u * (uint32_t)(line * ld);
 #pragma unroll
-      for (int t = 0; t < R; ++t) v[b][t] = src[lpad(jj + t * bfl)];
-      if (k != 0) {
+      for (int t = 0; t < R; ++t) {
+        v[b][t] = lds[pad_slot(q)];
+        q += dq_in;
+      }
+      if (Ns > 1) {  // uniform; the k = 0 entries are exactly 1
+        const Tw<T>* w = tw + (Ns - 2) + k * (R - 1);
 #pragma unroll
-        for (int t = 1; t < R; ++t) v[b][t] = twmul<S>(v[b][t], tw[k * t * twstep]);
+        for (int t = 1; t < R; ++t) v[b][t] = twmul<S>(v[b][t], w[t]);
       }
       dft<R, S, T>::run(v[b]);
       lbase[b] = line * ld;
@@ -98,16 +114,20 @@ __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, i
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
     if (lbase[b] >= 0) {
-      cx<T>* dst = lds + lbase[b];
+      uint32_t q = 17u * (uint32_t)obase[b] + 16u * (uint32_t)lbase[b];
 #pragma unroll
-      for (int t = 0; t < R; ++t) dst[lpad(obase[b] + t * Ns)] = v[b][t];
+      for (int t = 0; t < R; ++t) {
+        lds[pad_slot(q)] = v[b][t];
+        q += dq_out;
+      }
     }
   }
   __syncthreads();
 }
 
 // Full line transform of every line of the tile; S = -1 forward, +1 inverse
-// (unnormalised).  `tw` holds w_n^m = exp(-2 pi i m / n), m in [0, n).
+// (unnormalised).  `tw` is the stage-major twiddle table of `sch` (forward
+// sign, w_n = exp(-2 pi i / n); the inverse conjugates).
 // Must be called by every thread of the block (it synchronises).
 template <int S, typename T>
 __device__ __forceinline__ void lds_fft(cx<T>* lds, int ld, int nlines, const LineSchedule& sch,

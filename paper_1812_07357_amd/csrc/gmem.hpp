@@ -44,6 +44,11 @@ struct gm<float> {
   static __device__ __forceinline__ void stc(rsrc_t r, uint32_t i, cx<float> v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0, 0);
   }
+  // complex elements i and i + 1 in one 16-byte store
+  static __device__ __forceinline__ void stc2(rsrc_t r, uint32_t i, cx<float> a, cx<float> b) {
+    const u32x4 w = {__float_as_uint(a.re), __float_as_uint(a.im), __float_as_uint(b.re), __float_as_uint(b.im)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, i * 8u, 0, 0);
+  }
 };
 
 template <>
@@ -59,6 +64,10 @@ struct gm<double> {
   }
   static __device__ __forceinline__ void stc(rsrc_t r, uint32_t i, cx<double> v) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, i * 16u, 0, 0);
+  }
+  static __device__ __forceinline__ void stc2(rsrc_t r, uint32_t i, cx<double> a, cx<double> b) {
+    stc(r, i, a);
+    stc(r, i + 1u, b);
   }
 };
 

@@ -38,9 +38,9 @@ struct XFwdParams {
   int gather;            // 0: src is box shaped; 1: src is G1 (GX, GY, GZ) with wrap
   int GX, GY, GZ;
   int x0, y0, z0;        // (origin - nguard) mod G, non-negative
-  FastDiv fd_ytiles, fd_NZ, fd_NX, fd_GX, fd_GY, fd_GZ, fd_ty;
+  FastDiv fd_ytiles, fd_NZ, fd_NX, fd_GX, fd_GY, fd_GZ, fd_nc;
   int ld_drow, ld_dcol;  // block stride over (complex line, x) = divmod(threads, NX)
-  int wr_drow, wr_dcol;  // block stride over (kx, y)            = divmod(threads, ty)
+  int wr_drow, wr_dcol;  // block stride over (kx, complex line) = divmod(threads, ty / 2)
   LineFFT<T> fft;
 };
 
@@ -158,7 +158,8 @@ template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s);
 
 // Tables (FP64 math, stored at working precision).
-void launch_twiddles(void* dst, int n, int fp64, hipStream_t s);
+// Stage-major twiddle table of `sch` (see fft_lds.hpp), n entries allocated.
+void launch_twiddles(void* dst, const LineSchedule& sch, int fp64, hipStream_t s);
 void launch_bluestein(void* chirp, void* filt, int n, int m, int fp64, hipStream_t s);
 void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s);
 void launch_coef(void* coef, void* kxw, void* kyw, void* kzw, const double* kx, const double* ky,

@@ -141,29 +141,29 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
     __syncthreads();
     lds_line_fft<-1, T>(lds, ld, nc, p.fft);
 
-    // Split each complex line into the half spectra of its two real lines; y fastest.
+    // Split each complex line c into the half spectra of its two real lines
+    // (y = 2c and 2c + 1), written as one pair; y fastest.
     const rsrc_t dst = make_rsrc(p.dst + (i64)f * p.npts, p.dst_bytes);
     const int ny_t = min(ty, NY - ybase);
-    const int nwr = NXH * ty;
+    const int nwr = NXH * nc;
     Walk v;
-    v.row = fdiv(tid, p.fd_ty);
-    v.col = tid - v.row * ty;
-#pragma unroll 4
+    v.row = fdiv(tid, p.fd_nc);
+    v.col = tid - v.row * nc;
+#pragma unroll 2
     for (int e = tid; e < nwr; e += nth) {
-      const int kx = v.row, t = v.col;
-      const int c = t >> 1;
+      const int kx = v.row, c = v.col;
       const cx<T> za = lds[c * ld + lpad(kx)];
       const cx<T> zb = cconj(lds[c * ld + lpad(kx == 0 ? 0 : NX - kx)]);
-      cx<T> val;
-      if ((t & 1) == 0) {
-        val = cscale(cadd(za, zb), T(0.5));
-      } else {
-        const cx<T> d = csub(za, zb);
-        val = {T(0.5) * d.im, T(-0.5) * d.re};
-      }
-      const uint32_t o = (t < ny_t) ? (uint32_t)((z * NXH + kx) * NY + ybase + t) : kOOB;
-      gm<T>::stc(dst, o, val);
-      v.next(p.wr_drow, p.wr_dcol, ty);
+      const cx<T> sum = cadd(za, zb), dif = csub(za, zb);
+      const cx<T> va = cscale(sum, T(0.5));
+      const cx<T> vb = {T(0.5) * dif.im, T(-0.5) * dif.re};
+      const int t = 2 * c;
+      const uint32_t o = (uint32_t)((z * NXH + kx) * NY + ybase + t);
+      if (t + 1 < ny_t)
+        gm<T>::stc2(dst, o, va, vb);
+      else if (t < ny_t)
+        gm<T>::stc(dst, o, va);
+      v.next(p.wr_drow, p.wr_dcol, nc);
     }
     __syncthreads();
   }

@@ -293,7 +293,7 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   }
   hipStream_t s = nullptr;
   for (Axis* a : {&p->ax, &p->ay, &p->az}) {
-    launch_twiddles(a->tw, a->sch.n, p->fp64, s);
+    launch_twiddles(a->tw, a->sch, p->fp64, s);
     if (a->blue) launch_bluestein(a->chirp, a->filt, a->n, a->sch.n, p->fp64, s);
   }
   launch_modk(p->kd, p->NX, p->NXH, d->dx, d->order, s);
@@ -391,7 +391,7 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   x1.fd_ytiles = make_fastdiv(x1.ytiles);
   x1.fd_NZ = make_fastdiv(NZ);
   x1.fd_NX = make_fastdiv(NX);
-  x1.fd_ty = make_fastdiv(x1.ty);
+  x1.fd_nc = make_fastdiv(x1.ty / 2);
   if (io.gather) {
     x1.fd_GX = make_fastdiv(io.GX);
     x1.fd_GY = make_fastdiv(io.GY);
@@ -399,8 +399,8 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   }
   x1.ld_drow = nth / NX;
   x1.ld_dcol = nth % NX;
-  x1.wr_drow = nth / x1.ty;
-  x1.wr_dcol = nth % x1.ty;
+  x1.wr_drow = nth / (x1.ty / 2);
+  x1.wr_dcol = nth % (x1.ty / 2);
   x1.fft = line_fft<T>(p->ax);
 
   YPassParams<T>& y2 = sp.y2;
@@ -744,6 +744,7 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
     TuneEntry best_e{std::vector<int>(saved.radix, saved.radix + saved.nstages), saved_tile};
     for (auto& r : cands) {
       set_radices(&A.sch, r);
+      launch_twiddles(A.tw, A.sch, p->fp64, s);
       std::vector<int> tl;
       if (a == 0) {
         const int hi = std::min(fit_lines(A.sch, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
@@ -775,6 +776,7 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
       }
     }
     set_radices(&A.sch, best_e.radix);
+    launch_twiddles(A.tw, A.sch, p->fp64, s);
     if (a == 0) {
       p->ty1 = best_e.tile;
       p->ty5 = std::min(best_e.tile, 2 * std::max(1, ((pf / 2) * nth) / p->NXH));

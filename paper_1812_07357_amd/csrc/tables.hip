@@ -26,28 +26,41 @@ namespace {
 constexpr int kT = 256;
 
 // FP32 twiddles are stored as hi + lo float pairs (hi = rounded value, lo = rounded remainder).
-__global__ void k_twiddles_f32(Tw<float>* dst, int n) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  double s, c;
-  sincospi(-2.0 * (double)m / (double)n, &s, &c);
-  const float ch = (float)c, sh = (float)s;
-  dst[m] = {{ch, sh}, {(float)(c - (double)ch), (float)(s - (double)sh)}};
-}
-__global__ void k_twiddles_f64(Tw<double>* dst, int n) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n) return;
-  double s, c;
-  sincospi(-2.0 * (double)m / (double)n, &s, &c);
-  dst[m] = {{c, s}};
-}
-
 // Stores an FP64 complex value as a run-time twiddle of the working precision.
 __device__ inline void put_tw(Tw<float>* dst, int i, double c, double s) {
   const float ch = (float)c, sh = (float)s;
   dst[i] = {{ch, sh}, {(float)(c - (double)ch), (float)(s - (double)sh)}};
 }
 __device__ inline void put_tw(Tw<double>* dst, int i, double c, double s) { dst[i] = {{c, s}}; }
+
+// Stage-major twiddle table of a line schedule: entry (Ns - 1) + k (R - 1) + (t - 1)
+// of the stage with radix R and span Ns is w_n^m, m = t k n / (Ns R) < n,
+// evaluated in FP64 from the exact integer m.
+struct StagePlan {
+  int n, nstages;
+  int radix[kMaxStages];
+};
+
+template <typename T>
+__global__ void k_twiddles(Tw<T>* dst, StagePlan sp) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= sp.n - 1) return;
+  int Ns = 1;
+  for (int s = 0; s < sp.nstages; ++s) {
+    const int R = sp.radix[s];
+    if (e + 1 < Ns * R) {
+      const int local = e + 1 - Ns;
+      const int k = local / (R - 1), t = local - k * (R - 1) + 1;
+      const long long m = (long long)t * k * (sp.n / (Ns * R));
+      double sn, cs;
+      sincospi(-2.0 * (double)m / (double)sp.n, &sn, &cs);
+      put_tw(dst, e, cs, sn);
+      return;
+    }
+    Ns *= R;
+  }
+}
+
 
 // Bluestein chirp c[j] = exp(-i pi j^2 / n); j^2 is reduced modulo 2n exactly.
 template <typename T>
@@ -158,11 +171,14 @@ inline unsigned nblk(long long n) { return (unsigned)((n + kT - 1) / kT); }
 
 }  // namespace
 
-void launch_twiddles(void* dst, int n, int fp64, hipStream_t s) {
+void launch_twiddles(void* dst, const LineSchedule& sch, int fp64, hipStream_t s) {
+  StagePlan sp{sch.n, sch.nstages, {}};
+  for (int i = 0; i < sch.nstages; ++i) sp.radix[i] = sch.radix[i];
+  if (sch.n < 2) return;
   if (fp64)
-    hipLaunchKernelGGL(k_twiddles_f64, dim3(nblk(n)), dim3(kT), 0, s, (Tw<double>*)dst, n);
+    hipLaunchKernelGGL(k_twiddles<double>, dim3(nblk(sch.n)), dim3(kT), 0, s, (Tw<double>*)dst, sp);
   else
-    hipLaunchKernelGGL(k_twiddles_f32, dim3(nblk(n)), dim3(kT), 0, s, (Tw<float>*)dst, n);
+    hipLaunchKernelGGL(k_twiddles<float>, dim3(nblk(sch.n)), dim3(kT), 0, s, (Tw<float>*)dst, sp);
 }
 
 void launch_bluestein(void* chirp, void* filt, int n, int m, int fp64, hipStream_t s) {
