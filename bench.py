@@ -90,10 +90,16 @@ def algorithmic_bytes(box, interior, ng, s):
 
 
 def source_digest():
+    """Digest of the pass kernels' source with comments and blank space removed."""
+    import re
+
     h = hashlib.sha256()
-    for name in ("passes.hip", "fft_lds.hpp", "cplx.hpp", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1812_07357_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    for name in ("passes.hip", "fft_lds.hpp", "cplx.hpp", "internal.hpp", "gmem.hpp"):
+        with open(os.path.join(ROOT, "paper_1812_07357_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -14,12 +14,13 @@
 // and the inverse rebuilds Z = A + i B over the full line from the half
 // spectra (imaginary parts of the self-conjugate bins dropped).
 //
-// Every kernel is persistent and software-pipelined: a block loads tile t into
-// registers, moves it to LDS, issues the loads of its next tile (they stay in
-// flight while the LDS transform of tile t runs), writes tile t out, and
-// repeats.  All global accesses go through buffer resources with hardware range
-// checks (gmem.hpp); an index that is out of range by construction (kOOB) reads
-// zero and drops writes.
+// Every kernel is persistent: a block loads a tile into LDS (through registers,
+// in rounds of a few values per thread), transforms it, writes it out and takes
+// the next tile.  Blocks are small enough in registers (FP32: at most 128) that
+// several share a CU and overlap one another's loads, transforms and barriers.
+// All global accesses go through buffer resources with hardware range checks
+// (gmem.hpp); an index that is out of range by construction (kOOB) reads zero
+// and drops writes.
 //
 // Each pass body is written against a parameter source: a single box (the
 // parameters are the kernel argument) or a batch of boxes of different sizes
