@@ -76,11 +76,13 @@ struct ZPushParams {
   const T* ky;           // NY
   const T* kz;           // NZ
   int NY, NZ, NXH;
-  int ntiles;            // columns NXH * NY
+  int ncol;              // (kx, ky) columns per tile
+  int zgroup;            // lines per transform call (the lines of a tile are transformed in groups)
+  int ntiles;            // ceil(NXH * NY / ncol)
   int z_lo, z_hi;        // output z written: [z_lo, z_hi)
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
-  FastDiv fd_NY;
+  FastDiv fd_NY, fd_NZ, fd_ncol;
   LineFFT<T> fft;
 };
 

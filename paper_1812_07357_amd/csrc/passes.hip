@@ -286,15 +286,66 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
 // Push (Sec. 1.1; J constant over the step, rho at both ends):
 //   E' = C E + i c^2 S1 (K x B) - (S1/eps0) J + i (c^2/eps0) K (X3 rho_old - X2 rho_new)
 //   B' = C B - i S1 (K x E) + i (X1/eps0) (K x J)
-// A tile is one (kx, ky) column: its 11 z-lines are loaded into LDS,
-// transformed, pushed point by point, and the 6 lines of E and B transformed
-// back and stored over the interior z range.  Unlike the other passes this one
-// does not hold the next tile in registers: the transforms of 17 lines leave
-// no room for it, and small blocks with a 128-register cap (FP32) let several
-// columns per CU overlap each other's loads and barriers instead.
-// Each wave moves whole z-lines (lines w, w + nwaves, ...), so the field of a
-// wave's load is uniform and one buffer resource serves it.
-template <typename T, typename Src>
+// A tile is ncol consecutive (kx, ky) columns (one for long lines, several for
+// short ones): their 11 z-lines each are loaded into LDS, transformed, pushed
+// point by point, and the 6 lines of E and B per column transformed back and
+// stored over the interior z range.  LDS line f * ncol + c holds field f of
+// the tile's column c, so the E and B lines of all columns come first and the
+// inverse transform runs over one contiguous block of 6 ncol lines (the last
+// tile of a box may have fewer columns: its missing lines hold zeros).  This pass
+// does not hold the next tile in registers: the transforms leave no room for
+// it, and small blocks with a 128-register cap (FP32) let several tiles per CU
+// overlap each other's loads and barriers instead.
+// The push at one k-space point: column col (LDS lines of field f at
+// f * fs + cbase) and z index kz; k_x, k_y of the column given.
+template <typename T>
+__device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, int fs, int cbase, int col, int kz,
+                                           T kx, T ky) {
+  const T c2 = p.c2, ie = p.inv_eps0;
+  const uint32_t idx = (uint32_t)(col * p.NZ + kz);
+  T cc[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) cc[k] = gm<T>::ld(make_rsrc(p.coef + (i64)k * p.npts, p.coef_bytes), idx);
+  const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
+  const T kzz = p.kz[kz];
+  const int s = cbase + lpad(kz);
+  const cx<T> ex = lds[0 * fs + s], ey = lds[1 * fs + s], ez = lds[2 * fs + s];
+  const cx<T> bx = lds[3 * fs + s], by = lds[4 * fs + s], bz = lds[5 * fs + s];
+  const cx<T> jx = lds[6 * fs + s], jy = lds[7 * fs + s], jz = lds[8 * fs + s];
+  const cx<T> ro = lds[9 * fs + s], rn = lds[10 * fs + s];
+  // K x B, K x E, K x J (K real)
+  const cx<T> kbx = csub(cscale(bz, ky), cscale(by, kzz));
+  const cx<T> kby = csub(cscale(bx, kzz), cscale(bz, kx));
+  const cx<T> kbz = csub(cscale(by, kx), cscale(bx, ky));
+  const cx<T> kex = csub(cscale(ez, ky), cscale(ey, kzz));
+  const cx<T> key = csub(cscale(ex, kzz), cscale(ez, kx));
+  const cx<T> kez = csub(cscale(ey, kx), cscale(ex, ky));
+  const cx<T> kjx = csub(cscale(jz, ky), cscale(jy, kzz));
+  const cx<T> kjy = csub(cscale(jx, kzz), cscale(jz, kx));
+  const cx<T> kjz = csub(cscale(jy, kx), cscale(jx, ky));
+  const cx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
+  const T a = c2 * S1;   // multiplies K x B
+  const T g = c2 * ie;   // multiplies K r
+  const T sj = S1 * ie;  // multiplies J
+  const T xj = X1 * ie;  // multiplies K x J
+  // E' = C E - sj J + i (a K x B + g K r)
+  const cx<T> ux = cadd(cscale(kbx, a), cscale(rr, g * kx));
+  const cx<T> uy = cadd(cscale(kby, a), cscale(rr, g * ky));
+  const cx<T> uz = cadd(cscale(kbz, a), cscale(rr, g * kzz));
+  lds[0 * fs + s] = {C * ex.re - sj * jx.re - ux.im, C * ex.im - sj * jx.im + ux.re};
+  lds[1 * fs + s] = {C * ey.re - sj * jy.re - uy.im, C * ey.im - sj * jy.im + uy.re};
+  lds[2 * fs + s] = {C * ez.re - sj * jz.re - uz.im, C * ez.im - sj * jz.im + uz.re};
+  // B' = C B + i (xj K x J - S1 K x E)
+  const cx<T> wx = csub(cscale(kjx, xj), cscale(kex, S1));
+  const cx<T> wy = csub(cscale(kjy, xj), cscale(key, S1));
+  const cx<T> wz = csub(cscale(kjz, xj), cscale(kez, S1));
+  lds[3 * fs + s] = {C * bx.re - wx.im, C * bx.im + wx.re};
+  lds[4 * fs + s] = {C * by.re - wy.im, C * by.im + wy.re};
+  lds[5 * fs + s] = {C * bz.re - wz.im, C * bz.im + wz.re};
+}
+
+// MULTI = false compiles the single-column case (ncol == 1) without the column bookkeeping.
+template <typename T, bool MULTI, typename Src>
 __device__ __forceinline__ void zpush_body(const Src& S) {
   constexpr int kRound = 16;  // line chunks of 64 points loaded per thread before they go to LDS
   cx<T>* lds = lds_base<T>();
@@ -303,23 +354,28 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
   const int wave = uniform(tid >> 6);
   const int nwaves = nth >> 6;
   for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
-    int col;
-    const ZPushParams<T>& p = S.box(tile, col);
+    int lt;
+    const ZPushParams<T>& p = S.box(tile, lt);
     const int NZ = p.NZ;
     const int ld = fft_slots(p.fft.sch.n);
+    const int col0 = lt * p.ncol;
+    const int ncol = MULTI ? p.ncol : 1;
+    const int nct = MULTI ? min(ncol, p.NXH * p.NY - col0) : 1;  // columns present in this tile
+    const int nlines = 11 * ncol;
     const int per_line = (NZ + 63) >> 6;
-    const int items = ((11 - wave + nwaves - 1) / nwaves) * per_line;  // (line, chunk) pairs of this wave
+    const int items = ((nlines - wave + nwaves - 1) / nwaves) * per_line;  // (line, chunk) pairs of this wave
     for (int q0 = 0; q0 < items; q0 += kRound) {
       cx<T> r[kRound];
 #pragma unroll
       for (int u = 0; u < kRound; ++u) {
         const int q = q0 + u;
         const int sl = q / per_line, i = q - sl * per_line;
-        const int l = wave + sl * nwaves;
+        const int l = wave + sl * nwaves;  // LDS line: field l / ncol, column l % ncol
+        const int f = MULTI ? fdiv(l, p.fd_ncol) : l, c = MULTI ? l - f * ncol : 0;
         const int z = lane + 64 * i;
-        const bool ok = q < items && z < NZ;
-        const rsrc_t rb = make_rsrc(p.b + (i64)(ok ? l : 0) * p.npts, p.field_bytes);
-        r[u] = gm<T>::ldc(rb, ok ? (uint32_t)(col * NZ + z) : kOOB);
+        const bool ok = q < items && z < NZ && (!MULTI || c < nct);
+        const rsrc_t rb = make_rsrc(p.b + (i64)(ok ? f : 0) * p.npts, p.field_bytes);
+        r[u] = gm<T>::ldc(rb, ok ? (uint32_t)((col0 + c) * NZ + z) : kOOB);
       }
 #pragma unroll
       for (int u = 0; u < kRound; ++u) {
@@ -330,61 +386,47 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
       }
     }
     __syncthreads();
-    lds_line_fft<-1, T>(lds, ld, 11, p.fft);
+    // lines are independent: transform them in groups that fit the block's butterfly budget
+    if (p.zgroup >= nlines)
+      lds_line_fft<-1, T>(lds, ld, nlines, p.fft);
+    else
+      for (int l0 = 0; l0 < nlines; l0 += p.zgroup)
+        lds_line_fft<-1, T>(lds + l0 * ld, ld, min(p.zgroup, nlines - l0), p.fft);
 
-    const int kxi = fdiv(col, p.fd_NY);
-    const int kyi = col - kxi * p.NY;
-    const T kx = p.kx[kxi];
-    const T ky = p.ky[kyi];
-    const T c2 = p.c2, ie = p.inv_eps0;
-    for (int kz = tid; kz < NZ; kz += nth) {
-      const uint32_t idx = (uint32_t)(col * NZ + kz);
-      T cc[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) cc[c] = gm<T>::ld(make_rsrc(p.coef + (i64)c * p.npts, p.coef_bytes), idx);
-      const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
-      const T kzz = p.kz[kz];
-      const int s = lpad(kz);
-      const cx<T> ex = lds[0 * ld + s], ey = lds[1 * ld + s], ez = lds[2 * ld + s];
-      const cx<T> bx = lds[3 * ld + s], by = lds[4 * ld + s], bz = lds[5 * ld + s];
-      const cx<T> jx = lds[6 * ld + s], jy = lds[7 * ld + s], jz = lds[8 * ld + s];
-      const cx<T> ro = lds[9 * ld + s], rn = lds[10 * ld + s];
-      // K x B, K x E, K x J (K real)
-      const cx<T> kbx = csub(cscale(bz, ky), cscale(by, kzz));
-      const cx<T> kby = csub(cscale(bx, kzz), cscale(bz, kx));
-      const cx<T> kbz = csub(cscale(by, kx), cscale(bx, ky));
-      const cx<T> kex = csub(cscale(ez, ky), cscale(ey, kzz));
-      const cx<T> key = csub(cscale(ex, kzz), cscale(ez, kx));
-      const cx<T> kez = csub(cscale(ey, kx), cscale(ex, ky));
-      const cx<T> kjx = csub(cscale(jz, ky), cscale(jy, kzz));
-      const cx<T> kjy = csub(cscale(jx, kzz), cscale(jz, kx));
-      const cx<T> kjz = csub(cscale(jy, kx), cscale(jx, ky));
-      const cx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
-      const T a = c2 * S1;   // multiplies K x B
-      const T g = c2 * ie;   // multiplies K r
-      const T sj = S1 * ie;  // multiplies J
-      const T xj = X1 * ie;  // multiplies K x J
-      // E' = C E - sj J + i (a K x B + g K r)
-      const cx<T> ux = cadd(cscale(kbx, a), cscale(rr, g * kx));
-      const cx<T> uy = cadd(cscale(kby, a), cscale(rr, g * ky));
-      const cx<T> uz = cadd(cscale(kbz, a), cscale(rr, g * kzz));
-      lds[0 * ld + s] = {C * ex.re - sj * jx.re - ux.im, C * ex.im - sj * jx.im + ux.re};
-      lds[1 * ld + s] = {C * ey.re - sj * jy.re - uy.im, C * ey.im - sj * jy.im + uy.re};
-      lds[2 * ld + s] = {C * ez.re - sj * jz.re - uz.im, C * ez.im - sj * jz.im + uz.re};
-      // B' = C B + i (xj K x J - S1 K x E)
-      const cx<T> wx = csub(cscale(kjx, xj), cscale(kex, S1));
-      const cx<T> wy = csub(cscale(kjy, xj), cscale(key, S1));
-      const cx<T> wz = csub(cscale(kjz, xj), cscale(kez, S1));
-      lds[3 * ld + s] = {C * bx.re - wx.im, C * bx.im + wx.re};
-      lds[4 * ld + s] = {C * by.re - wy.im, C * by.im + wy.re};
-      lds[5 * ld + s] = {C * bz.re - wz.im, C * bz.im + wz.re};
+    const int fs = ncol * ld;  // LDS distance between the lines of consecutive fields
+    if (!MULTI || 2 * NZ > nth) {
+      // long lines: one column at a time, its k_x and k_y uniform
+      for (int c = 0; c < nct; ++c) {
+        const int col = col0 + c;
+        const int kxi = fdiv(col, p.fd_NY);
+        const int kyi = col - kxi * p.NY;
+        const T kx = p.kx[kxi], ky = p.ky[kyi];
+        for (int kz = tid; kz < NZ; kz += nth) push_point(p, lds, fs, c * ld, col, kz, kx, ky);
+      }
+    } else {
+      // short lines: (column, k_z) pairs spread over the block
+      for (int e = tid; e < nct * NZ; e += nth) {
+        const int c = fdiv(e, p.fd_NZ);
+        const int kz = e - c * NZ;
+        const int col = col0 + c;
+        const int kxi = fdiv(col, p.fd_NY);
+        const int kyi = col - kxi * p.NY;
+        push_point(p, lds, fs, c * ld, col, kz, p.kx[kxi], p.ky[kyi]);
+      }
     }
     __syncthreads();
-    lds_line_fft<1, T>(lds, ld, 6, p.fft);
+    if (p.zgroup >= 6 * ncol)
+      lds_line_fft<1, T>(lds, ld, 6 * ncol, p.fft);
+    else
+      for (int l0 = 0; l0 < 6 * ncol; l0 += p.zgroup)
+        lds_line_fft<1, T>(lds + l0 * ld, ld, min(p.zgroup, 6 * ncol - l0), p.fft);
 
-    for (int l = wave; l < 6; l += nwaves) {
-      const rsrc_t rb = make_rsrc(p.b + (i64)l * p.npts, p.field_bytes);
-      for (int z = p.z_lo + lane; z < p.z_hi; z += 64) gm<T>::stc(rb, (uint32_t)(col * NZ + z), lds[l * ld + lpad(z)]);
+    for (int l = wave; l < 6 * ncol; l += nwaves) {
+      const int f = MULTI ? fdiv(l, p.fd_ncol) : l, c = MULTI ? l - f * ncol : 0;
+      if (MULTI && c >= nct) continue;
+      const rsrc_t rb = make_rsrc(p.b + (i64)f * p.npts, p.field_bytes);
+      for (int z = p.z_lo + lane; z < p.z_hi; z += 64)
+        gm<T>::stc(rb, (uint32_t)((col0 + c) * NZ + z), lds[l * ld + lpad(z)]);
     }
     __syncthreads();
   }
@@ -502,16 +544,17 @@ __global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_
 k_ypass_b(BatchArgs<YPassParams<T>> a) {
   ypass_body<S, T>(BatchSrc<YPassParams<T>>{a});
 }
-// z pass: at most 128 registers in FP32 (4 waves per SIMD), 256 in FP64 (2).
-template <typename T, int NTH>
-__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+// z pass: FP32 single-box tiles fit 96 registers (5 waves per SIMD), batched ones 128 (4);
+// FP64 256 (2).
+template <typename T, int NTH, bool MULTI>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2)))
 k_zpush(ZPushParams<T>) {
-  zpush_body<T>(SingleSrc<ZPushParams<T>>{});
+  zpush_body<T, MULTI>(SingleSrc<ZPushParams<T>>{});
 }
 template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_zpush_b(BatchArgs<ZPushParams<T>> a) {
-  zpush_body<T>(BatchSrc<ZPushParams<T>>{a});
+  zpush_body<T, true>(BatchSrc<ZPushParams<T>>{a});
 }
 // x inverse: at most 128 registers in FP32 (two blocks per CU).
 template <typename T>
@@ -578,7 +621,7 @@ size_t ypass_lds(const YPassParams<T>& p) {
 }
 template <typename T>
 size_t zpush_lds(const ZPushParams<T>& p) {
-  return (size_t)11 * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+  return (size_t)11 * p.ncol * fft_slots(p.fft.sch.n) * cx_bytes<T>();
 }
 template <typename T>
 size_t xinv_lds(const XInvParams<T>& p) {
@@ -596,14 +639,21 @@ void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
   else
     launch_persistent(k_ypass<-1, T>, p, kLineThreads, ypass_lds(p), p.ntiles, s);
 }
+template <typename T, bool MULTI>
+void launch_zpush_cols(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
+  if (nthreads == kZThreads[0])
+    launch_persistent(k_zpush<T, kZThreads[0], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
+  else if (nthreads == kZThreads[1])
+    launch_persistent(k_zpush<T, kZThreads[1], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
+  else
+    launch_persistent(k_zpush<T, kZThreads[2], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
+}
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
-  if (nthreads == kZThreads[0])
-    launch_persistent(k_zpush<T, kZThreads[0]>, p, nthreads, zpush_lds(p), p.ntiles, s);
-  else if (nthreads == kZThreads[1])
-    launch_persistent(k_zpush<T, kZThreads[1]>, p, nthreads, zpush_lds(p), p.ntiles, s);
+  if (p.ncol == 1)
+    launch_zpush_cols<T, false>(p, nthreads, s);
   else
-    launch_persistent(k_zpush<T, kZThreads[2]>, p, nthreads, zpush_lds(p), p.ntiles, s);
+    launch_zpush_cols<T, true>(p, nthreads, s);
 }
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s) {

@@ -165,6 +165,7 @@ struct psatd_plan {
   int ty5 = 0;       // real y-lines per P5 tile
   int nl_y = 0;      // lines per P2/P4 tile
   int zthreads = 0;  // threads of the P3 block
+  int zcols = 0;     // (kx, ky) columns per P3 tile
   double* kd = nullptr;  // FP64 modified k: kx (NXH), ky (NY), kz (NZ)
   void* kw = nullptr;    // same at working precision
   void* coef = nullptr;  // 5 * npts
@@ -222,6 +223,39 @@ int validate(const psatd_plan_desc* d) {
   return PSATD_OK;
 }
 
+// Lines per tile: about one block's worth of elements for long lines, more
+// lines for short ones (many small boxes), always within LDS and the
+// one-butterfly-round-per-radix register budget checked by fit_lines.
+int x_line_cap(int n) { return std::max(8, 4608 / n); }   // complex x-lines (pairs of real lines)
+int y_line_cap(int n) { return std::max(16, 5120 / n); }
+// LDS a z tile may use: the device limit for one column, 64 KB for several.
+size_t z_lds(int cols) { return cols > 1 ? std::min<size_t>(64 * 1024, lds_limit()) : lds_limit(); }
+
+// A z tile of `cols` columns must hold its 11 cols lines in LDS; the block of
+// zt threads transforms them in groups, so it only needs room for the
+// butterflies of one line per round.
+bool z_fits(const LineSchedule& s, int zt, int em, size_t cs, int cols) {
+  return (size_t)11 * cols * lds_line(s.n) * cs <= z_lds(cols) && fit_lines(s, zt, em, cs, 1, SIZE_MAX) >= 1;
+}
+// Lines a block of zt threads transforms per call.
+int z_group(const LineSchedule& s, int zt, int em, size_t cs, int nlines) {
+  return std::max(1, fit_lines(s, zt, em, cs, nlines, SIZE_MAX));
+}
+
+// Columns and threads of a z tile: about 320 points of line per tile, the
+// smallest block that fits.
+void choose_z_tile(psatd_plan* p, const LineSchedule& szs, int em, size_t cs) {
+  p->zthreads = 0;
+  p->zcols = 0;
+  for (int c = std::max(1, std::min(16, 320 / p->NZ)); c >= 1 && !p->zthreads; --c)
+    for (int zt : kZThreads)
+      if (z_fits(szs, zt, em, cs, c)) {
+        p->zthreads = zt;
+        p->zcols = c;
+        break;
+      }
+}
+
 int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   int rc = validate(d);
   if (rc) return rc;
@@ -244,24 +278,16 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   const LineSchedule& sxs = p->ax.sch;
   const LineSchedule& sys = p->ay.sch;
   const LineSchedule& szs = p->az.sch;
-  // Tiles of the x and y passes stay within 64 KB (several workgroups per CU)
-  // and within the per-thread prefetch budget; the z pass must hold all 11
-  // lines of a column and may use the device limit.
+  // Tiles of the x and y passes stay within 64 KB (several workgroups per CU);
+  // a z tile holds all 11 lines of each of its columns and may use the device
+  // limit when it has a single column.
   const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
-  const int pf = p->fp64 ? prefetch_budget<double>::v : prefetch_budget<float>::v;
   const int nth = kLineThreads;
-  const int nc1 = std::min(fit_lines(sxs, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
-  const int nc5 = std::min(fit_lines(sxs, nth, em, cs, 8, lds_small), ((pf / 2) * nth) / p->NXH);
+  const int nc1 = fit_lines(sxs, nth, em, cs, x_line_cap(p->NX), lds_small);
   p->ty1 = 2 * std::max(nc1, 0);
-  p->ty5 = 2 * std::max(nc5, 0);
-  p->nl_y = std::min(fit_lines(sys, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
-  p->zthreads = 0;
-  for (int zt : kZThreads) {
-    if (fit_lines(szs, zt, em, cs, 11, lds_limit()) == 11) {
-      p->zthreads = zt;
-      break;
-    }
-  }
+  p->ty5 = p->ty1;
+  p->nl_y = fit_lines(sys, nth, em, cs, y_line_cap(p->NY), lds_small);
+  choose_z_tile(p, szs, em, cs);
   if (p->ty1 <= 0 || p->ty5 <= 0 || p->nl_y <= 0 || p->zthreads == 0) {
     free_plan(p);
     return fail(PSATD_EUNSUPPORTED, "box %dx%dx%d does not fit the LDS / register tiling of this build", p->NX,
@@ -440,12 +466,16 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   z3.NY = NY;
   z3.NZ = NZ;
   z3.NXH = NXH;
-  z3.ntiles = NXH * NY;
+  z3.ncol = p->zcols;
+  z3.zgroup = z_group(p->az.sch, p->zthreads, emax<T>::v, sizeof(cx<T>), 11 * p->zcols);
+  z3.ntiles = (NXH * NY + p->zcols - 1) / p->zcols;
   z3.z_lo = io.z_lo;
   z3.z_hi = io.z_hi;
   z3.c2 = T(p->d.c * p->d.c);
   z3.inv_eps0 = T(1.0 / p->d.eps0);
   z3.fd_NY = make_fastdiv(NY);
+  z3.fd_NZ = make_fastdiv(NZ);
+  z3.fd_ncol = make_fastdiv(p->zcols);
   z3.fft = line_fft<T>(p->az);
 
   YPassParams<T>& y4 = sp.y4;
@@ -719,7 +749,6 @@ float time_axis(psatd_plan* p, int ax, int reps, hipStream_t s) {
 template <typename T>
 int autotune_plan(psatd_plan* p, hipStream_t s) {
   const int em = emax<T>::v;
-  const int pf = prefetch_budget<T>::v;
   const size_t cs = sizeof(cx<T>);
   const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
   const int nth = kLineThreads;
@@ -747,21 +776,21 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
       launch_twiddles(A.tw, A.sch, p->fp64, s);
       std::vector<int> tl;
       if (a == 0) {
-        const int hi = std::min(fit_lines(A.sch, nth, em, cs, 8, lds_small), (pf * nth) / p->NX);
+        const int hi = fit_lines(A.sch, nth, em, cs, x_line_cap(p->NX), lds_small);
         for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(2 * t);
       } else if (a == 1) {
-        const int hi = std::min(fit_lines(A.sch, nth, em, cs, 16, lds_small), (pf * nth) / p->NY);
+        const int hi = fit_lines(A.sch, nth, em, cs, y_line_cap(p->NY), lds_small);
         for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(t);
       } else {
         for (int zt : kZThreads)
-          if (fit_lines(A.sch, zt, em, cs, 11, lds_limit()) == 11 && tl.size() < 2) tl.push_back(zt);
+          if (z_fits(A.sch, zt, em, cs, p->zcols) && tl.size() < 2) tl.push_back(zt);
       }
       if (hit != tune_cache().end()) tl = {hit->second.tile};
       for (int t : tl) {
         if (t <= 0) continue;
         if (a == 0) {
           p->ty1 = t;
-          p->ty5 = std::min(t, 2 * std::max(1, ((pf / 2) * nth) / p->NXH));
+          p->ty5 = t;
         } else if (a == 1) {
           p->nl_y = t;
         } else {
@@ -779,7 +808,7 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
     launch_twiddles(A.tw, A.sch, p->fp64, s);
     if (a == 0) {
       p->ty1 = best_e.tile;
-      p->ty5 = std::min(best_e.tile, 2 * std::max(1, ((pf / 2) * nth) / p->NXH));
+      p->ty5 = best_e.tile;
     } else if (a == 1) {
       p->nl_y = best_e.tile;
     } else {

@@ -133,3 +133,78 @@ def test_precision_study_box_fp32_and_fp64(lib):
     assert _rel_max(got, exact) <= 1e-11
     got, exact = res[("fp32", 1)]
     assert _rel_l2(got, exact) <= 2e-6 and _rel_max(got, exact) <= 2e-5
+
+
+def test_precision_study_vacuum_200_steps(lib):
+    """Precision study on the 1024x512x512 + 16 box, p = 32, 200 steps, FP32 and FP64.
+
+    Vacuum (J = rho = 0) with transverse modes: E of each mode is orthogonal to
+    its modified wave vector K_p, B = K_p-hat x E / c, so the exact evolution
+    keeps i K_p . E = 0 and conserves the field energy mode by mode.  Reported
+    per precision: relative L2 error per vector field against the exact
+    evolution (sampled cells), energy drift |W - W0| / W0 over the whole grid,
+    and the Gauss residual ||K_p . E^|| / (||K_p|| ||E^||) from a grid FFT.
+    Gates: FP64 error <= 1e-10, drift <= 1e-11; FP32 error <= 2e-5 per vector
+    field after 200 steps, drift <= 1e-4; Gauss residual <= 1e-12 (FP64) and
+    <= 1e-5 (FP32).
+    """
+    import torch
+
+    from oracle import kspace
+
+    interior, ng, order, period, d, dt = (1024, 512, 512), 16, 32, 32, 1.0, 0.5
+    nx, ny, nz = interior
+    gshape = (nz, ny, nx)
+    rng = np.random.default_rng(7)
+    nmodes = 6
+    m = _draw_modes(rng, period, nmodes)
+    kvec = 2 * np.pi * m / (period * d)
+    kp = np.stack([kspace.modified_k_at(kvec[:, a], d, order) for a in range(3)], axis=1)
+    coefs = np.zeros((11, nmodes), dtype=np.complex128)
+    for j in range(nmodes):
+        u = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        khat = kp[j] / np.linalg.norm(kp[j])
+        e = u - khat * (khat @ u)
+        coefs[0:3, j] = e
+        coefs[3:6, j] = np.cross(khat, e)
+    g64 = _synthesize_gpu(kvec, coefs, gshape, d)
+    ncell = nx * ny * nz
+    w0 = ncell * 2.0 * float(np.sum(np.abs(coefs[0:6]) ** 2))  # Parseval for distinct real modes
+    k, j, i = _sample_points(rng, gshape, 20000)
+    pos = np.stack([i * d, j * d, k * d], axis=1)
+    kt, jt, it = (torch.as_tensor(a, device="cuda") for a in (k, j, i))
+    exact = modes.synthesize(kvec, modes.push_modes(kvec, coefs, d, dt, order, nsteps=200), pos)
+    # modified wave numbers of the G1 grid's half spectrum, for the Gauss residual
+    kx = torch.as_tensor(kspace.modified_k(nx, d, order)[: nx // 2 + 1], device="cuda")
+    ky = torch.as_tensor(kspace.modified_k(ny, d, order), device="cuda")
+    kz = torch.as_tensor(kspace.modified_k(nz, d, order), device="cuda")
+    report = {}
+    for precision in ("fp64", "fp32"):
+        plan = lib.Plan(nx, ny, nz, nguard=ng, order=order, dx=d, dt=dt, precision=precision)
+        g = g64.to(plan.dtype, copy=True).contiguous()
+        for _ in range(200):
+            plan.step_g1(g, (0, 0, 0))
+        torch.cuda.synchronize()
+        plan.close()
+        got = g[0:6][:, kt, jt, it].double().cpu().numpy()
+        w = float(sum(float((g[c].double() ** 2).sum()) for c in range(6)))
+        div = None
+        norm = None
+        for c, kc in enumerate((kx[None, None, :], ky[None, :, None], kz[:, None, None])):
+            f = torch.fft.rfftn(g[c].double())
+            div = kc * f if div is None else div + kc * f
+            a = f.abs() ** 2
+            norm = a if norm is None else norm + a
+            del f, a
+        kk = kx[None, None, :] ** 2 + ky[None, :, None] ** 2 + kz[:, None, None] ** 2
+        gauss = float(torch.sqrt((div.abs() ** 2).sum() / (kk * norm).sum()))
+        del div, norm, kk, g
+        torch.cuda.empty_cache()
+        report[precision] = {"E": _rel_l2(got[0:3], exact[0:3]), "B": _rel_l2(got[3:6], exact[3:6]),
+                             "energy_drift": abs(w - w0) / w0, "gauss": gauss}
+        print(f"  {precision} 200 steps: E {report[precision]['E']:.2e} B {report[precision]['B']:.2e} "
+              f"energy drift {report[precision]['energy_drift']:.2e} Gauss {gauss:.2e}", flush=True)
+    r = report["fp64"]
+    assert r["E"] <= 1e-10 and r["B"] <= 1e-10 and r["energy_drift"] <= 1e-11 and r["gauss"] <= 1e-12
+    r = report["fp32"]
+    assert r["E"] <= 2e-5 and r["B"] <= 2e-5 and r["energy_drift"] <= 1e-4 and r["gauss"] <= 1e-5
