@@ -264,6 +264,62 @@ def summarize_pmc(directory, steps, out_json):
     print(json.dumps(rec, indent=1))
 
 
+def run_extra(steps=20):
+    """Timing of the other workloads (parity cases, not the headline) and of rocFFT on the same transforms.
+
+    - 32^3 periodic grid, exact k (order 0), no guards, FP64 (launch-bound);
+    - 1024x512x512 + 16 guards (box 1056x544x544), order 32, FP32 and FP64;
+    - the 17 real 3D transforms of the 576x320x320 box alone (11 forward
+      R2C, 6 inverse C2R) through torch.fft, i.e. rocFFT: a timing comparison,
+      never part of the path.
+    """
+    import torch
+
+    from paper_1812_07357_amd import psatd
+
+    def time_plan(interior, ng, order, precision, nsteps):
+        nx, ny, nz = interior
+        plan = psatd.Plan(nx, ny, nz, nguard=ng, order=order, dx=DX, dt=DT, precision=precision)
+        dtype = torch.float64 if precision == "fp64" else torch.float32
+        g = torch.randn((11, nz, ny, nx), dtype=dtype, device="cuda")
+        for _ in range(3):
+            plan.step_g1(g, (0, 0, 0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            plan.step_g1(g, (0, 0, 0))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / nsteps
+        box = plan.box
+        plan.close()
+        del g
+        torch.cuda.empty_cache()
+        return {"ms_per_step": ms, "interior_cell_updates_per_s": nx * ny * nz / (ms * 1e-3),
+                "box_cell_updates_per_s": box[0] * box[1] * box[2] / (ms * 1e-3)}
+
+    out = {"32^3 exact k FP64": time_plan((32, 32, 32), 0, 0, "fp64", 10 * steps)}
+    for prec in ("fp32", "fp64"):
+        out[f"1024x512x512+16 p=32 {prec.upper()}"] = time_plan((1024, 512, 512), 16, 32, prec, steps)
+    nx, ny, nz = (n + 2 * NGUARD for n in INTERIOR)
+    for prec, dtype in (("FP32", torch.float32), ("FP64", torch.float64)):
+        a = torch.randn((11, nz, ny, nx), dtype=dtype, device="cuda")
+        for _ in range(2):
+            spec = torch.fft.rfftn(a, dim=(1, 2, 3))
+            back = torch.fft.irfftn(spec[0:6], s=(nz, ny, nx), dim=(1, 2, 3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            spec = torch.fft.rfftn(a, dim=(1, 2, 3))
+            back = torch.fft.irfftn(spec[0:6], s=(nz, ny, nx), dim=(1, 2, 3))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[f"rocFFT 17 transforms of the 576x320x320 box {prec}"] = {
+            "ms": ms, "note": "transforms only (no push, no guard fill/merge), torch.fft on ROCm"}
+        del a, spec, back
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +330,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the 32^3 and 1024x512x512 workloads and rocFFT on the same transforms")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="write profiles/hbm_traffic_config2_fp32.json from rocprofv3 --pmc runs under DIR and exit")
     args = ap.parse_args()
@@ -373,6 +431,10 @@ def main():
     if not args.no_batch:
         log("batch run (64 uneven boxes, hipGraph)")
         out["batch_fp32"] = run_batch(50)
+
+    if args.extra:
+        log("extra workloads and rocFFT comparison")
+        out["extra"] = run_extra()
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
