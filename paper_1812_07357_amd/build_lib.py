@@ -31,15 +31,22 @@ FLAGS = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
-SOURCES = ["passes.hip", "tables.hip", "guards.hip", "plan.hip", "mlp.hip"]
+# (source, object name, extra flags).  passes.hip is compiled once per
+# (pass, precision) unit so that the large pass kernels build in parallel.
+_PASS_UNITS = [(u, name, prec) for u, name in ((1, "xfwd"), (2, "ypass"), (3, "zpush"), (4, "zpush_batch"),
+                                               (5, "xinv")) for prec in ("float", "double")]
+SOURCES = [("passes.hip", f"passes_{name}_{prec}", [f"-DPSATD_UNIT={u}", f"-DPSATD_REAL={prec}"])
+           for u, name, prec in _PASS_UNITS]
+SOURCES += [(src, os.path.splitext(src)[0], []) for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip")]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit) -> str:
+    src, name, extra = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-8000:]}")
+        raise RuntimeError(f"hipcc failed on {src} ({name}):\n{r.stderr[-8000:]}")
     return obj
 
 

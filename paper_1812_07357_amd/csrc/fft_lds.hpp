@@ -73,8 +73,9 @@ __host__ __device__ __forceinline__ int lds_line(int n) { return (lpad(n - 1) + 
 template <int R, int S, typename T>
 __device__ __forceinline__ void stockham_stage(cx<T>* lds, int ld, int nlines, int n, int Ns, const FastDiv& fb,
                                                const FastDiv& fn, const Tw<T>* __restrict__ tw) {
-  constexpr int MB = emax<T>::v / R;
-  static_assert(MB >= 1, "radix larger than the register budget");
+  // butterflies per thread: as many as the register budget holds, at least one
+  // (radices above the budget hold one butterfly of R values)
+  constexpr int MB = emax<T>::v / R > 0 ? emax<T>::v / R : 1;
   const int bfl = (int)fb.d;
   const int total = nlines * bfl;
   const int nth = blockDim.x;
@@ -148,8 +149,16 @@ __device__ __forceinline__ void lds_fft(cx<T>* lds, int ld, int nlines, const Li
       case 9: stockham_stage<9, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
       case 11: stockham_stage<11, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
       case 13: stockham_stage<13, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 6: stockham_stage<6, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 10: stockham_stage<10, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 12: stockham_stage<12, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
       case 16: stockham_stage<16, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
       case 17: stockham_stage<17, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 18: stockham_stage<18, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 20: stockham_stage<20, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 24: stockham_stage<24, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 32: stockham_stage<32, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
+      case 36: stockham_stage<36, S, T>(lds, ld, nlines, n, Ns, fb, fn, tw); break;
       default: break;  // the host never schedules another radix
     }
     Ns *= R;

@@ -113,8 +113,8 @@ struct XInvParams {
 
 // Threads per block of each pass and register budgets of the tile prefetch.
 constexpr int kLineThreads = 512;
-// Block sizes of the z pass (tried in this order; the first whose 11 lines fit is used).
-constexpr int kZThreads[3] = {256, 512, 1024};
+// Block sizes of the z pass (tried in this order; the first whose line butterflies fit is used).
+constexpr int kZThreads[2] = {256, 512};
 template <typename T>
 struct prefetch_budget;  // complex values per thread held for the next tile
 template <>

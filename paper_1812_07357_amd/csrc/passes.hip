@@ -643,10 +643,8 @@ template <typename T, bool MULTI>
 void launch_zpush_cols(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
   if (nthreads == kZThreads[0])
     launch_persistent(k_zpush<T, kZThreads[0], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
-  else if (nthreads == kZThreads[1])
-    launch_persistent(k_zpush<T, kZThreads[1], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
   else
-    launch_persistent(k_zpush<T, kZThreads[2], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
+    launch_persistent(k_zpush<T, kZThreads[1], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
 }
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
@@ -675,10 +673,8 @@ template <typename T>
 void launch_zpush_batch(const BatchArgs<ZPushParams<T>>& a, int nthreads, size_t lds, hipStream_t s) {
   if (nthreads == kZThreads[0])
     launch_persistent(k_zpush_b<T, kZThreads[0]>, a, nthreads, lds, a.total, s);
-  else if (nthreads == kZThreads[1])
-    launch_persistent(k_zpush_b<T, kZThreads[1]>, a, nthreads, lds, a.total, s);
   else
-    launch_persistent(k_zpush_b<T, kZThreads[2]>, a, nthreads, lds, a.total, s);
+    launch_persistent(k_zpush_b<T, kZThreads[1]>, a, nthreads, lds, a.total, s);
 }
 template <typename T>
 void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_t s) {
@@ -686,21 +682,34 @@ void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_
 }
 
 
-#define PSATD_INSTANTIATE(T)                                                                      \
-  template void launch_xfwd<T>(const XFwdParams<T>&, hipStream_t);                                \
-  template void launch_ypass<T>(const YPassParams<T>&, int, hipStream_t);                         \
-  template void launch_zpush<T>(const ZPushParams<T>&, int, hipStream_t);                         \
-  template void launch_xinv<T>(const XInvParams<T>&, hipStream_t);                                \
-  template void launch_xfwd_batch<T>(const BatchArgs<XFwdParams<T>>&, size_t, hipStream_t);       \
+// Explicit instantiations.  The build compiles this file once per (pass, precision)
+// unit (-DPSATD_UNIT=1..5 -DPSATD_REAL=float|double) so that the units compile in
+// parallel; without PSATD_UNIT everything is instantiated here.
+#define PSATD_INST_1(T)                                                                     \
+  template void launch_xfwd<T>(const XFwdParams<T>&, hipStream_t);                          \
+  template void launch_xfwd_batch<T>(const BatchArgs<XFwdParams<T>>&, size_t, hipStream_t); \
+  template size_t xfwd_lds<T>(const XFwdParams<T>&);
+#define PSATD_INST_2(T)                                                                               \
+  template void launch_ypass<T>(const YPassParams<T>&, int, hipStream_t);                             \
   template void launch_ypass_batch<T>(const BatchArgs<YPassParams<T>>&, int, size_t, hipStream_t); \
-  template void launch_zpush_batch<T>(const BatchArgs<ZPushParams<T>>&, int, size_t, hipStream_t); \
-  template void launch_xinv_batch<T>(const BatchArgs<XInvParams<T>>&, size_t, hipStream_t);       \
-  template size_t xfwd_lds<T>(const XFwdParams<T>&);                                              \
-  template size_t ypass_lds<T>(const YPassParams<T>&);                                            \
-  template size_t zpush_lds<T>(const ZPushParams<T>&);                                            \
+  template size_t ypass_lds<T>(const YPassParams<T>&);
+#define PSATD_INST_3(T)                                                   \
+  template void launch_zpush<T>(const ZPushParams<T>&, int, hipStream_t); \
+  template size_t zpush_lds<T>(const ZPushParams<T>&);
+#define PSATD_INST_4(T) \
+  template void launch_zpush_batch<T>(const BatchArgs<ZPushParams<T>>&, int, size_t, hipStream_t);
+#define PSATD_INST_5(T)                                                                     \
+  template void launch_xinv<T>(const XInvParams<T>&, hipStream_t);                          \
+  template void launch_xinv_batch<T>(const BatchArgs<XInvParams<T>>&, size_t, hipStream_t); \
   template size_t xinv_lds<T>(const XInvParams<T>&);
-PSATD_INSTANTIATE(float)
-PSATD_INSTANTIATE(double)
-#undef PSATD_INSTANTIATE
+#define PSATD_CAT2(a, b) a##b
+#define PSATD_CAT(a, b) PSATD_CAT2(a, b)
+#if defined(PSATD_UNIT) && defined(PSATD_REAL)
+PSATD_CAT(PSATD_INST_, PSATD_UNIT)(PSATD_REAL)
+#else
+#define PSATD_INST_ALL(T) PSATD_INST_1(T) PSATD_INST_2(T) PSATD_INST_3(T) PSATD_INST_4(T) PSATD_INST_5(T)
+PSATD_INST_ALL(float)
+PSATD_INST_ALL(double)
+#endif
 
 }  // namespace psatd

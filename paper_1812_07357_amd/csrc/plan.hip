@@ -59,39 +59,100 @@ size_t lds_limit() {
 
 
 // Factor n into compiled radices, largest powers of two first.
-bool make_schedule(int n, int emax, LineSchedule* s) {
+// Radices with compiled stages, and the VALU instructions per element one stage
+// of that radix costs (gfx950, FP32, twiddles included; measured on the stage
+// code).  A stage also costs an LDS round trip and two barriers, charged as
+// kStageCost; the first stage applies no twiddles.
+constexpr int kRadix[] = {36, 32, 24, 20, 18, 17, 16, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+double radix_cost(int r) {
+  switch (r) {
+    case 2: return 26.0;
+    case 3: return 28.3;
+    case 4: return 25.2;
+    case 5: return 31.0;
+    case 6: return 30.8;
+    case 7: return 34.4;
+    case 8: return 27.1;
+    case 9: return 35.0;
+    case 10: return 34.9;
+    case 11: return 41.9;
+    case 12: return 31.8;
+    case 13: return 45.8;
+    case 16: return 30.3;
+    case 17: return 53.6;
+    case 18: return 39.8;
+    case 20: return 37.9;
+    case 24: return 36.9;
+    case 32: return 34.7;
+    case 36: return 42.8;
+    default: return 1e9;
+  }
+}
+constexpr double kStageCost = 4.0;
+constexpr int kMaxSearchStages = 6;
+
+double schedule_cost(const std::vector<int>& r) {
+  double c = 0.0;
+  for (size_t i = 0; i < r.size(); ++i) c += radix_cost(r[i]) + kStageCost;
+  if (!r.empty()) c -= 8.0 * (r[0] - 1) / r[0];
+  return c;
+}
+
+// All factorisations of n into compiled radices (non-increasing), at most kMaxSearchStages stages.
+void factorisations(int n, int start, std::vector<int>& cur, std::vector<std::vector<int>>& out) {
+  if (n == 1) {
+    out.push_back(cur);
+    return;
+  }
+  if ((int)cur.size() == kMaxSearchStages) return;
+  for (size_t i = start; i < sizeof(kRadix) / sizeof(kRadix[0]); ++i)
+    if (n % kRadix[i] == 0) {
+      cur.push_back(kRadix[i]);
+      factorisations(n / kRadix[i], (int)i, cur, out);
+      cur.pop_back();
+    }
+}
+
+// Radix sequences for n, cheapest first (by schedule_cost), largest radix first
+// and, as alternatives, smallest first; at most `cap` of them.
+std::vector<std::vector<int>> ranked_schedules(int n, size_t cap) {
+  std::vector<std::vector<int>> sets, out;
+  std::vector<int> cur;
+  if (n > 1) factorisations(n, 0, cur, sets);
+  std::sort(sets.begin(), sets.end(), [](const std::vector<int>& x, const std::vector<int>& y) {
+    const double cx = schedule_cost(x), cy = schedule_cost(y);
+    return cx != cy ? cx < cy : x.size() < y.size();
+  });
+  for (const auto& s : sets) {
+    if (out.size() >= cap) break;
+    out.push_back(s);
+    std::vector<int> rev(s.rbegin(), s.rend());
+    if (rev != s && out.size() < cap) out.push_back(rev);
+  }
+  return out;
+}
+
+bool set_schedule(int n, const std::vector<int>& r, LineSchedule* s) {
   std::memset(s, 0, sizeof *s);
   s->n = n;
-  int m = n;
-  std::vector<int> r;
-  const int pow2[] = {16, 8, 4, 2};
-  for (int p : pow2)
-    while (m % p == 0 && p <= emax) {
-      r.push_back(p);
-      m /= p;
-    }
-  while (m % 9 == 0) {
-    r.push_back(9);
-    m /= 9;
-  }
-  const int odd[] = {3, 5, 7, 11, 13, 17};
-  for (int p : odd)
-    while (m % p == 0 && p <= emax) {
-      r.push_back(p);
-      m /= p;
-    }
-  if (m != 1 || (int)r.size() > kMaxStages) return false;
-  if (r.empty()) r.push_back(1);  // n == 1
-  s->nstages = (int)r.size();
-  if (n == 1) s->nstages = 0;
+  if ((int)r.size() > kMaxStages) return false;
+  s->nstages = n == 1 ? 0 : (int)r.size();
   int span = 1;
-  for (size_t i = 0; i < r.size() && n > 1; ++i) {
+  for (int i = 0; i < s->nstages; ++i) {
     s->radix[i] = r[i];
     s->bfl[i] = make_fastdiv((uint32_t)(n / r[i]));
     s->ns[i] = make_fastdiv((uint32_t)span);
     span *= r[i];
   }
   return true;
+}
+
+// The default schedule of length n: the cheapest factorisation (see ranked_schedules).
+bool make_schedule(int n, int emax, LineSchedule* s) {
+  (void)emax;
+  if (n == 1) return set_schedule(1, {}, s);
+  const auto r = ranked_schedules(n, 1);
+  return !r.empty() && set_schedule(n, r[0], s);
 }
 
 // One transform axis of a box: direct stages over n, or Bluestein over a padded
@@ -140,7 +201,7 @@ int fit_lines(const LineSchedule& s, int nth, int emax, size_t csize, int cap, s
       const int R = s.radix[i];
       const long long bf = (long long)nl * (s.n / R);
       const long long per = (bf + nth - 1) / nth;
-      if (per > emax / R) ok = false;
+      if (per > std::max(1, emax / R)) ok = false;  // one butterfly per thread above the budget
     }
     if (ok) return nl;
   }
@@ -585,49 +646,11 @@ int dispatch_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
 // keeps the fastest.  Results are cached per (precision, axis role, line
 // length, the two other box lengths) in memory and optionally in a JSON file.
 
-// Radix sequences for n (all factors compiled), at most `cap` of them, the
-// default factorisation first.
+// Radix sequences the autotuner times for n: the cost model's best few, the
+// default first.
 std::vector<std::vector<int>> radix_candidates(int n, int emax, size_t cap) {
-  std::vector<std::vector<int>> out;
-  LineSchedule s;
-  if (!make_schedule(n, emax, &s) || s.nstages == 0) return out;
-  std::vector<int> base(s.radix, s.radix + s.nstages);
-  out.push_back(base);
-  int p2 = 0, m = n;
-  while (m % 2 == 0) {
-    m /= 2;
-    ++p2;
-  }
-  std::vector<int> odd;
-  for (int r : base)
-    if (r % 2) odd.push_back(r);
-  // splits of 2^p2 into 16/8/4/2 factors
-  std::vector<std::vector<int>> splits;
-  const int pw[] = {16, 8, 4, 2};
-  const int lg[] = {4, 3, 2, 1};
-  std::vector<int> cur;
-  std::function<void(int, int)> rec = [&](int left, int start) {
-    if (left == 0) {
-      splits.push_back(cur);
-      return;
-    }
-    for (int i = start; i < 4; ++i)
-      if (lg[i] <= left && pw[i] <= emax) {
-        cur.push_back(pw[i]);
-        rec(left - lg[i], i);
-        cur.pop_back();
-      }
-  };
-  rec(p2, 0);
-  for (auto& sp : splits) {
-    std::vector<int> a = sp, b = odd, c;
-    a.insert(a.end(), odd.begin(), odd.end());  // powers of two first
-    b.insert(b.end(), sp.begin(), sp.end());    // odd radices first
-    c.assign(a.rbegin(), a.rend());             // smallest radices first
-    for (auto* v : {&a, &b, &c})
-      if (std::find(out.begin(), out.end(), *v) == out.end() && out.size() < cap) out.push_back(*v);
-  }
-  return out;
+  (void)emax;
+  return ranked_schedules(n, cap);
 }
 
 void set_radices(LineSchedule* s, const std::vector<int>& r) {
