@@ -19,9 +19,9 @@ using i64 = long long;
 // consecutive lines (a short contiguous run per position) on the other.
 
 // Every pass runs as a persistent kernel: a grid sized to the resident capacity
-// walks over the pass's tiles, and while one tile is transformed in LDS the
-// loads of the block's next tile are already in flight.  Arrays are addressed
-// through buffer resources (see gmem.hpp), one resource per field.
+// walks over the pass's tiles; several blocks share a CU and overlap one
+// another's loads, transforms and barriers.  Arrays are addressed through
+// buffer resources (see gmem.hpp), one resource per field.
 
 // P1: x-axis real-to-complex transform of pairs of y-lines (two real lines form
 // one complex line), box arrays or a periodic gather from G1, into layout A.
@@ -111,16 +111,18 @@ struct XInvParams {
   LineFFT<T> fft;
 };
 
-// Threads per block of each pass and register budgets of the tile prefetch.
+// Threads per block of the x and y passes.
 constexpr int kLineThreads = 512;
 // Block sizes of the z pass (tried in this order; the first whose line butterflies fit is used).
 constexpr int kZThreads[2] = {256, 512};
+// Complex values a thread loads from global memory before moving them to LDS
+// (one round of a tile load; a tile takes as many rounds as it needs).
 template <typename T>
-struct prefetch_budget;  // complex values per thread held for the next tile
+struct load_round;
 template <>
-struct prefetch_budget<float> { static constexpr int v = 12; };
+struct load_round<float> { static constexpr int v = 12; };
 template <>
-struct prefetch_budget<double> { static constexpr int v = 12; };
+struct load_round<double> { static constexpr int v = 12; };
 
 // A batch of boxes for one pass: per-box parameters in device memory; the tiles
 // of box b are numbered starts[b] .. starts[b+1]-1 (starts[nbox] == total).

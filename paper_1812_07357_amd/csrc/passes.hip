@@ -85,12 +85,11 @@ struct BatchSrc {
 
 // ------------------------------------------------------------------ P1
 // Tiles are ty consecutive y rows of one (field, z) plane, packed as ty/2
-// complex lines.  Loads go straight to LDS (in rounds that keep up to one
-// prefetch budget of values in flight per thread); overlap comes from several
-// blocks per CU.
+// complex lines.  Loads go to LDS in rounds of load_round values per thread;
+// overlap comes from several blocks per CU.
 template <typename T, typename Src>
 __device__ __forceinline__ void xfwd_body(const Src& S) {
-  constexpr int kRound = prefetch_budget<T>::v;  // element pairs loaded per thread before they go to LDS
+  constexpr int kRound = load_round<T>::v;  // element pairs loaded per thread before they go to LDS
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
 
@@ -171,11 +170,11 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
 }
 
 // ------------------------------------------------------------------ P2 / P4
-// Tiles are up to 16 y-lines; loads go straight to LDS in rounds of one
-// prefetch budget per thread, and several blocks per CU overlap each other.
+// Tiles are y-lines (about 5k elements); loads go to LDS in rounds of
+// load_round values per thread, and several blocks per CU overlap each other.
 template <int S_, typename T, typename Src>
 __device__ __forceinline__ void ypass_body(const Src& S) {
-  constexpr int kRound = prefetch_budget<T>::v;
+  constexpr int kRound = load_round<T>::v;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
 
@@ -437,7 +436,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
 // lines; loads go straight to LDS in rounds, several blocks per CU overlap.
 template <typename T, typename Src>
 __device__ __forceinline__ void xinv_body(const Src& S) {
-  constexpr int kRound = prefetch_budget<T>::v / 2;  // two values per element
+  constexpr int kRound = load_round<T>::v / 2;  // two values per element
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x, nth = blockDim.x;
 
