@@ -170,13 +170,25 @@ bool make_axis(int n, int emax, Axis* a) {
   a->n = n;
   a->blue = 0;
   if (make_schedule(n, emax, &a->sch)) return true;
-  for (int m = 2 * n - 1; m <= 8 * n; ++m) {
-    if (make_schedule(m, emax, &a->sch)) {
-      a->blue = 1;
-      return true;
+  // Bluestein: among padded lengths 2n - 1 <= m <= 4n, the one whose transform
+  // costs least (m times the per-element cost of its best schedule): a slightly
+  // longer m with two cheap stages beats the shortest m with three costly ones.
+  int best_m = 0;
+  double best = 0.0;
+  for (int m = 2 * n - 1; m <= 4 * n; ++m) {
+    const auto r = ranked_schedules(m, 1);
+    if (r.empty()) continue;
+    const double c = m * schedule_cost(r[0]);
+    if (!best_m || c < best) {
+      best = c;
+      best_m = m;
     }
   }
-  return false;
+  for (int m = 4 * n + 1; !best_m && m <= 8 * n; ++m)
+    if (!ranked_schedules(m, 1).empty()) best_m = m;
+  if (!best_m || !make_schedule(best_m, emax, &a->sch)) return false;
+  a->blue = 1;
+  return true;
 }
 
 template <typename T>
