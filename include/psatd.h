@@ -274,6 +274,16 @@ int psatd_mlp_train(psatd_mlp* mlp, const float* X, const float* target, int n, 
 /* Releases the network (NULL-safe; synchronise its stream first). */
 void psatd_mlp_destroy(psatd_mlp* mlp);
 
+/* Default line-transform schedule of this build for a box edge of n cells
+ * (host only, no GPU needed): the radices of the Stockham stages, in order,
+ * written to radices[0 .. max_radices-1], and in *transform_len the length
+ * they transform: n itself when every prime factor of n has a compiled radix
+ * (at most 17), otherwise the padded length m >= 2n - 1 of Bluestein's
+ * chirp-z form.  The factorisation is the cheapest under the build's per-stage
+ * cost model; plans start from it and the autotuner may reorder or replace it.
+ * Returns the number of stages, or PSATD_EINVAL / PSATD_EUNSUPPORTED. */
+int psatd_default_schedule(int n, int* radices, int max_radices, int* transform_len);
+
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char* psatd_last_error(void);
 

@@ -1074,6 +1074,17 @@ psatd_plan* psatd_plan_create(int nx, int ny, int nz, int nguard, int order, dou
 
 void psatd_plan_destroy(psatd_plan* plan) { free_plan(plan); }
 
+int psatd_default_schedule(int n, int* radices, int max_radices, int* transform_len) {
+  if (n < 1 || n > (1 << 24) || !radices || !transform_len || max_radices < 1)
+    return fail(PSATD_EINVAL, "psatd_default_schedule: n = %d, max_radices = %d", n, max_radices);
+  Axis a;
+  if (!make_axis(n, emax<float>::v, &a)) return fail(PSATD_EUNSUPPORTED, "no schedule for n = %d", n);
+  if (a.sch.nstages > max_radices) return fail(PSATD_EINVAL, "%d stages do not fit max_radices", a.sch.nstages);
+  for (int i = 0; i < a.sch.nstages; ++i) radices[i] = a.sch.radix[i];
+  *transform_len = a.sch.n;
+  return a.sch.nstages;
+}
+
 int psatd_plan_query(const psatd_plan* p, int what, long long* value) {
   if (!p || !value) return fail(PSATD_EINVAL, "NULL argument");
   switch (what) {

@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_mlp_train.argtypes = [vp, vp, vp, cint, vp, cint, cint, cf, cf, cf, cf, vp, vp]
     lib.psatd_mlp_destroy.restype = None
     lib.psatd_mlp_destroy.argtypes = [vp]
+    lib.psatd_default_schedule.restype = cint
+    lib.psatd_default_schedule.argtypes = [cint, ip, cint, ip]
     lib.psatd_last_error.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     return lib
@@ -502,3 +504,12 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def default_schedule(n: int):
+    """(radices, transform length) of the build's default line schedule for an edge of n cells (host only)."""
+    r = (ctypes.c_int * 16)()
+    m = ctypes.c_int()
+    ns = _lib.psatd_default_schedule(int(n), r, 16, ctypes.byref(m))
+    _check(ns if ns < 0 else PSATD_OK)
+    return [r[i] for i in range(ns)], m.value

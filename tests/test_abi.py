@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -88,3 +89,41 @@ def test_mlp_null_and_invalid_arguments(lib):
     assert L.psatd_mlp_train(None, None, None, 4, None, 1, 4, 1e-3, 0.9, 0.999, 1e-8, None, None) == lib.PSATD_EINVAL
     L.psatd_mlp_destroy(None)  # NULL-safe
     assert "psatd_mlp" in L.psatd_last_error().decode()
+
+
+def _factor(n):
+    out, p = [], 2
+    while p * p <= n:
+        while n % p == 0:
+            out.append(p)
+            n //= p
+        p += 1
+    if n > 1:
+        out.append(n)
+    return out
+
+
+RADICES = {2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 17, 18, 20, 24, 32, 36}
+
+
+def test_default_schedules_factor_the_length(lib):
+    """Host schedule choice: a product of compiled radices equal to n (smooth n) or to a Bluestein length >= 2n-1."""
+    for n in list(range(2, 300)) + [320, 544, 576, 1056, 1021, 2048, 4096, 6561]:
+        radices, m = lib.default_schedule(n)
+        assert radices and all(r in RADICES for r in radices), (n, radices)
+        assert int(np.prod(radices)) == m, (n, radices, m)
+        smooth = max(_factor(n)) <= 17
+        if smooth:
+            assert m == n, (n, radices, m)
+        else:
+            assert 2 * n - 1 <= m <= 4 * n, (n, m)
+    assert lib.default_schedule(320)[0] in ([20, 16], [16, 20])
+    assert len(lib.default_schedule(576)[0]) == 2
+    assert lib.default_schedule(1)[1] == 1
+
+
+def test_default_schedule_rejects_bad_arguments(lib):
+    r = (ctypes.c_int * 4)()
+    m = ctypes.c_int()
+    assert lib._lib.psatd_default_schedule(0, r, 4, ctypes.byref(m)) == lib.PSATD_EINVAL
+    assert lib._lib.psatd_default_schedule(64, None, 4, ctypes.byref(m)) == lib.PSATD_EINVAL
