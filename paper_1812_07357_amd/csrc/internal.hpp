@@ -36,6 +36,8 @@ struct XFwdParams {
   int ty;                // real y-lines per tile (even)
   int ytiles, ntiles;    // tiles per (field, z) and in total
   int gather;            // 0: src is box shaped; 1: src is G1 (GX, GY, GZ) with wrap
+  int xtab;              // gather through a per-tile LDS table (wrapped x of every column,
+                         // G1 offset of every real row) placed after the tile's lines
   int GX, GY, GZ;
   int x0, y0, z0;        // (origin - nguard) mod G, non-negative
   FastDiv fd_ytiles, fd_NZ, fd_NX, fd_GX, fd_GY, fd_GZ, fd_nc;

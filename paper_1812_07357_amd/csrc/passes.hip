@@ -44,6 +44,8 @@ __device__ inline cx<T>* lds_base() {
 
 // x mod d for 0 <= x < 2^31
 __device__ __forceinline__ int fmod_i(int x, const FastDiv& f) { return x - fdiv(x, f) * (int)f.d; }
+// x mod d for 0 <= x < 2 d
+__device__ __forceinline__ int wrap_once(int x, int d) { return x - (x >= d ? d : 0); }
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ------------------------------------------------------------------ parameter sources
@@ -107,6 +109,14 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
       const rsrc_t src = make_rsrc(p.src[f], p.src_bytes);
       const int zrow = p.gather ? fmod_i(p.z0 + z, p.fd_GZ) * p.GY : z * NY;
       const int rowlen = p.gather ? p.GX : NX;
+      // Gather table, after the tile's lines: the wrapped x of every column, then the G1
+      // offset of every real row of the tile, so the loads below need no divisions.
+      int* tab = reinterpret_cast<int*>(lds + nc * ld);
+      if (p.xtab) {
+        for (int i = tid; i < NX + ty; i += nth)
+          tab[i] = i < NX ? fmod_i(p.x0 + i, p.fd_GX) : (zrow + fmod_i(p.y0 + ybase + (i - NX), p.fd_GY)) * rowlen;
+        __syncthreads();
+      }
       Walk w;
       w.row = fdiv(tid, p.fd_NX);
       w.col = tid - w.row * NX;
@@ -119,13 +129,19 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
           if (e0 + tid + u * nth < nld) {
             const int ya = ybase + 2 * w.row;
             int xs = w.col, ra = ya, rb = ya + 1;
-            if (p.gather) {
-              xs = fmod_i(p.x0 + w.col, p.fd_GX);
-              ra = fmod_i(p.y0 + ya, p.fd_GY);
-              rb = fmod_i(p.y0 + ya + 1, p.fd_GY);
+            if (p.xtab) {
+              const int xt = tab[w.col];
+              if (ya < NY) ia = (uint32_t)(tab[NX + 2 * w.row] + xt);
+              if (ya + 1 < NY) ib = (uint32_t)(tab[NX + 2 * w.row + 1] + xt);
+            } else {
+              if (p.gather) {
+                xs = fmod_i(p.x0 + w.col, p.fd_GX);
+                ra = fmod_i(p.y0 + ya, p.fd_GY);
+                rb = fmod_i(p.y0 + ya + 1, p.fd_GY);
+              }
+              if (ya < NY) ia = (uint32_t)((zrow + ra) * rowlen + xs);
+              if (ya + 1 < NY) ib = (uint32_t)((zrow + rb) * rowlen + xs);
             }
-            if (ya < NY) ia = (uint32_t)((zrow + ra) * rowlen + xs);
-            if (ya + 1 < NY) ib = (uint32_t)((zrow + rb) * rowlen + xs);
           }
           re[u] = gm<T>::ld(src, ia);
           im[u] = gm<T>::ld(src, ib);
@@ -509,9 +525,11 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
         if (ya < p.y_hi) ia = (uint32_t)((zrow + ya) * rowlen + n);
         if (ya + 1 < p.y_hi) ib = (uint32_t)((zrow + ya + 1) * rowlen + n);
       } else if (n >= p.gx && n < p.gx + p.nx) {
-        const int xg = fmod_i(p.ox + n - p.gx, p.fd_GX);
-        if (ya < p.y_hi) ia = (uint32_t)((zrow + fmod_i(p.oy + ya - p.gy, p.fd_GY)) * rowlen + xg);
-        if (ya + 1 < p.y_hi) ib = (uint32_t)((zrow + fmod_i(p.oy + ya + 1 - p.gy, p.fd_GY)) * rowlen + xg);
+        // the interior is no larger than the grid and its origin lies in it: one wrap at most
+        const int xg = wrap_once(p.ox + n - p.gx, p.GX);
+        const int ra = wrap_once(p.oy + ya - p.gy, p.GY);
+        if (ya < p.y_hi) ia = (uint32_t)((zrow + ra) * rowlen + xg);
+        if (ya + 1 < p.y_hi) ib = (uint32_t)((zrow + wrap_once(ra + 1, p.GY)) * rowlen + xg);
       }
       gm<T>::st(dst, ia, val.re);
       gm<T>::st(dst, ib, val.im);
@@ -612,7 +630,8 @@ void launch_persistent(K kernel, const A& arg, int threads, size_t lds, int ntil
 // ------------------------------------------------------------------ launchers
 template <typename T>
 size_t xfwd_lds(const XFwdParams<T>& p) {
-  return (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+  const size_t lines = (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+  return lines + (p.xtab ? (size_t)(p.NX + p.ty) * sizeof(int) : 0);
 }
 template <typename T>
 size_t ypass_lds(const YPassParams<T>& p) {

@@ -235,6 +235,7 @@ struct psatd_plan {
   size_t rsize = 0;  // bytes per real
   Axis ax, ay, az;   // transform axes x, y, z
   int ty1 = 0;       // real y-lines per P1 tile
+  bool xtab = false; // P1 tiles leave LDS room for the gather table
   int ty5 = 0;       // real y-lines per P5 tile
   int nl_y = 0;      // lines per P2/P4 tile
   int zthreads = 0;  // threads of the P3 block
@@ -300,6 +301,9 @@ int validate(const psatd_plan_desc* d) {
 // lines for short ones (many small boxes), always within LDS and the
 // one-butterfly-round-per-radix register budget checked by fit_lines.
 int x_line_cap(int n) { return std::max(8, 4608 / n); }   // complex x-lines (pairs of real lines)
+// LDS of the P1 gather table for a box of NX cells along x: one int per column and per real row
+// of the largest tile, rounded to 16 bytes.
+size_t x_table_bytes(int NX) { return ((size_t)(NX + 2 * x_line_cap(NX)) * 4 + 15) & ~(size_t)15; }
 int y_line_cap(int n) { return std::max(16, 5120 / n); }
 // LDS a z tile may use: the device limit for one column, 64 KB for several.
 size_t z_lds(int cols) { return cols > 1 ? std::min<size_t>(64 * 1024, lds_limit()) : lds_limit(); }
@@ -356,7 +360,10 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   // limit when it has a single column.
   const size_t lds_small = std::min<size_t>(64 * 1024, lds_limit());
   const int nth = kLineThreads;
-  const int nc1 = fit_lines(sxs, nth, em, cs, x_line_cap(p->NX), lds_small);
+  // P1 tiles leave room for the gather table when a tile of at least one line still fits.
+  int nc1 = fit_lines(sxs, nth, em, cs, x_line_cap(p->NX), lds_small - x_table_bytes(p->NX));
+  p->xtab = nc1 >= 1;
+  if (!p->xtab) nc1 = fit_lines(sxs, nth, em, cs, x_line_cap(p->NX), lds_small);
   p->ty1 = 2 * std::max(nc1, 0);
   p->ty5 = p->ty1;
   p->nl_y = fit_lines(sys, nth, em, cs, y_line_cap(p->NY), lds_small);
@@ -481,6 +488,7 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   x1.ytiles = (NY + x1.ty - 1) / x1.ty;
   x1.ntiles = 11 * NZ * x1.ytiles;
   x1.gather = io.gather;
+  x1.xtab = io.gather && p->xtab;
   x1.GX = io.GX;
   x1.GY = io.GY;
   x1.GZ = io.GZ;
@@ -811,7 +819,8 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
       launch_twiddles(A.tw, A.sch, p->fp64, s);
       std::vector<int> tl;
       if (a == 0) {
-        const int hi = fit_lines(A.sch, nth, em, cs, x_line_cap(p->NX), lds_small);
+        const int hi =
+            fit_lines(A.sch, nth, em, cs, x_line_cap(p->NX), lds_small - (p->xtab ? x_table_bytes(p->NX) : 0));
         for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(2 * t);
       } else if (a == 1) {
         const int hi = fit_lines(A.sch, nth, em, cs, y_line_cap(p->NY), lds_small);
