@@ -50,6 +50,9 @@ def _boxes():
         ((53, 29, 23), 0, 8),        # prime edges > 17 on every axis (chirp-z transforms)
         ((219, 40, 60), 2, 32),      # box 223 x 44 x 64: prime x edge of the uneven-box range
         ((33, 41, 45), 7, 64),       # box 47 x 55 x 59: 47, 59 prime; 55 = 5 * 11
+        ((1, 6, 5), 0, 0),           # degenerate: one cell along x (half spectrum of one bin)
+        ((2, 1, 3), 0, 2),           # degenerate: one cell along y, Nyquist-only x
+        ((1, 1, 1), 0, 0),           # a single cell: only k = 0
     ]
 
 
@@ -124,6 +127,7 @@ def test_push_nonunit_constants_fp64(lib):
     ((16, 20, 24), (12, 10, 8), 3, (17, 13, 11), 16),     # box wrapping around the edges
     ((10, 12, 14), (6, 8, 4), 9, (5, 2, 7), 0),           # guards wider than the grid (multi-hop)
     ((12, 18, 22), (22, 18, 12), 0, (0, 0, 0), 32),       # no guards: the global solve
+    ((6, 8, 1), (1, 4, 3), 2, (0, 5, 4), 4),              # one-cell x axis: every x guard wraps onto it
 ])
 def test_step_g1_matches_oracle(lib, precision, gshape, interior, ng, origin, order):
     import torch
