@@ -59,6 +59,35 @@ def test_batch_step_matches_oracle(lib, precision):
     batch.close()
 
 
+def _edge_decomposition(case):
+    if case == "single":
+        # one box covering the whole grid, its guards wrapping onto itself
+        return (12, 10, 8), [{"origin": (3, 4, 5), "interior": (12, 10, 8), "nguard": 3, "order": 4}]
+    # a one-cell-wide slab next to a wide box
+    return (9, 7, 5), [{"origin": (0, 0, 0), "interior": (1, 7, 5), "nguard": 2, "order": 8},
+                       {"origin": (1, 0, 0), "interior": (8, 7, 5), "nguard": 1, "order": 0}]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["single", "slab"])
+def test_batch_edge_decompositions_match_oracle(lib, precision, case):
+    import torch
+
+    gdims, boxes = _edge_decomposition(case)
+    d, dt = 1.0, 0.5
+    g1 = synth.random_fields(synth.rng_for(303, len(boxes)), gdims[::-1])
+    ref = domain.local_steps(g1, boxes, 2, d, dt)
+    batch = lib.Batch(boxes, gdims, dx=d, dt=dt, precision=precision)
+    g = _to_gpu(g1, batch.dtype)
+    batch.step(g)
+    batch.step(g)
+    torch.cuda.synchronize()
+    got = g.double().cpu().numpy()
+    err = np.abs(got[0:6] - ref[0:6]).max() / np.abs(ref[0:6]).max()
+    assert err <= (1e-12 if precision == "fp64" else 3e-5), err
+    batch.close()
+
+
 def test_batch_equals_boxes_advanced_one_by_one(lib):
     """Each batched box gives bitwise the result of its own plan on a snapshot of the step-n fields."""
     import torch
