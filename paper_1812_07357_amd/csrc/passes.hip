@@ -551,8 +551,10 @@ __global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_
 k_xfwd_b(BatchArgs<XFwdParams<T>> a) {
   xfwd_body<T>(BatchSrc<XFwdParams<T>>{a});
 }
+// y passes (single box): FP32 capped at 80 registers, three blocks per CU.  The
+// spills this costs are cheaper than the lost latency hiding of two blocks.
 template <int S, typename T>
-__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1)))
 k_ypass(YPassParams<T>) {
   ypass_body<S, T>(SingleSrc<YPassParams<T>>{});
 }
