@@ -16,7 +16,8 @@
 //
 // Every kernel is persistent: a block loads a tile into LDS (through registers,
 // in rounds of a few values per thread), transforms it, writes it out and takes
-// the next tile.  Blocks are small enough in registers (FP32: at most 128) that
+// the next tile.  Blocks are small enough in registers (FP32: at most 128, 96 for
+// the z pass and 80 for the single-box y pass, whatever that costs in spills) that
 // several share a CU and overlap one another's loads, transforms and barriers.
 // All global accesses go through buffer resources with hardware range checks
 // (gmem.hpp); an index that is out of range by construction (kOOB) reads zero
@@ -309,8 +310,8 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
 // inverse transform runs over one contiguous block of 6 ncol lines (the last
 // tile of a box may have fewer columns: its missing lines hold zeros).  This pass
 // does not hold the next tile in registers: the transforms leave no room for
-// it, and small blocks with a 128-register cap (FP32) let several tiles per CU
-// overlap each other's loads and barriers instead.
+// it, and small blocks with a 96-register cap (FP32, five per CU) let several
+// tiles per CU overlap each other's loads and barriers instead.
 // The push at one k-space point: column col (LDS lines of field f at
 // f * fs + cbase) and z index kz; k_x, k_y of the column given.
 template <typename T>
