@@ -108,13 +108,17 @@ struct XInvParams {
   int gx, gy, gz;        // guard widths
   int nx;                // interior cells along x
   FastDiv fd_ytiles, fd_nz, fd_nc, fd_NX, fd_GX, fd_GY, fd_GZ;
-  int ld_drow, ld_dcol;  // block stride over (kx, complex line) = divmod(threads, ty/2)
-  int wr_drow, wr_dcol;  // block stride over (complex line, x)  = divmod(threads, NX)
+  int nthreads;          // block size the tile was fitted for (kXInvThreads, or kLineThreads
+                         // when a line's butterflies exceed the smaller block)
   LineFFT<T> fft;
 };
 
 // Threads per block of the x and y passes.
 constexpr int kLineThreads = 512;
+// Threads per block of the x inverse pass: its tiles hold the same lines as the
+// x forward pass's (as far as the butterfly budget allows) in smaller blocks, so
+// more of them share a CU; lines too long for it fall back to kLineThreads.
+constexpr int kXInvThreads = 256;
 // Block sizes of the z pass (tried in this order; the first whose line butterflies fit is used).
 constexpr int kZThreads[2] = {256, 512};
 // Complex values a thread loads from global memory before moving them to LDS
@@ -152,7 +156,7 @@ void launch_ypass_batch(const BatchArgs<YPassParams<T>>& a, int inverse, size_t 
 template <typename T>
 void launch_zpush_batch(const BatchArgs<ZPushParams<T>>& a, int nthreads, size_t lds, hipStream_t s);
 template <typename T>
-void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_t s);
+void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, int nthreads, size_t lds, hipStream_t s);
 
 template <typename T>
 void launch_xfwd(const XFwdParams<T>& p, hipStream_t s);

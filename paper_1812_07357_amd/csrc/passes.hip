@@ -474,6 +474,7 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
       Walk w;
       w.row = fdiv(tid, p.fd_nc);  // (kx, complex line)
       w.col = tid - w.row * nc;
+      const int ldr = fdiv(nth, p.fd_nc), ldc = nth - ldr * nc;  // block stride over (kx, complex line)
       for (int e0 = 0; e0 < nld; e0 += kRound * nth) {
         cx<T> av[kRound], bv[kRound];
         Walk w0 = w;
@@ -487,7 +488,7 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
           }
           av[u] = gm<T>::ldc(src, ia);
           bv[u] = gm<T>::ldc(src, ib);
-          w.next(p.ld_drow, p.ld_dcol, nc);
+          w.next(ldr, ldc, nc);
         }
 #pragma unroll
         for (int u = 0; u < kRound; ++u) {
@@ -502,7 +503,7 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
             lds[c * ld + lpad(kx)] = {x.re - y.im, x.im + y.re};
             if (!selfconj) lds[c * ld + lpad(NX - kx)] = {x.re + y.im, y.re - x.im};
           }
-          w0.next(p.ld_drow, p.ld_dcol, nc);
+          w0.next(ldr, ldc, nc);
         }
       }
     }
@@ -516,6 +517,7 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
     Walk v;
     v.row = fdiv(tid, p.fd_NX);  // (complex line, x)
     v.col = tid - v.row * NX;
+    const int wdr = fdiv(nth, p.fd_NX), wdc = nth - wdr * NX;  // block stride over (complex line, x)
 #pragma unroll 4
     for (int e = tid; e < nwr; e += nth) {
       const int c = v.row, n = v.col;
@@ -534,7 +536,7 @@ __device__ __forceinline__ void xinv_body(const Src& S) {
       }
       gm<T>::st(dst, ia, val.re);
       gm<T>::st(dst, ib, val.im);
-      v.next(p.wr_drow, p.wr_dcol, NX);
+      v.next(wdr, wdc, NX);
     }
     __syncthreads();
   }
@@ -576,14 +578,15 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof
 k_zpush_b(BatchArgs<ZPushParams<T>> a) {
   zpush_body<T, true>(BatchSrc<ZPushParams<T>>{a});
 }
-// x inverse: at most 128 registers in FP32 (two blocks per CU).
-template <typename T>
-__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+// x inverse: at most 128 registers in FP32; 256-thread blocks (four per CU) unless
+// the lines need the larger block.
+template <typename T, int NTH>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 k_xinv(XInvParams<T>) {
   xinv_body<T>(SingleSrc<XInvParams<T>>{});
 }
-template <typename T>
-__global__ void __launch_bounds__(kLineThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+template <typename T, int NTH>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 k_xinv_b(BatchArgs<XInvParams<T>> a) {
   xinv_body<T>(BatchSrc<XInvParams<T>>{a});
 }
@@ -676,7 +679,10 @@ void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
 }
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
-  launch_persistent(k_xinv<T>, p, kLineThreads, xinv_lds(p), p.ntiles, s);
+  if (p.nthreads == kXInvThreads)
+    launch_persistent(k_xinv<T, kXInvThreads>, p, kXInvThreads, xinv_lds(p), p.ntiles, s);
+  else
+    launch_persistent(k_xinv<T, kLineThreads>, p, kLineThreads, xinv_lds(p), p.ntiles, s);
 }
 
 template <typename T>
@@ -698,8 +704,11 @@ void launch_zpush_batch(const BatchArgs<ZPushParams<T>>& a, int nthreads, size_t
     launch_persistent(k_zpush_b<T, kZThreads[1]>, a, nthreads, lds, a.total, s);
 }
 template <typename T>
-void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_t s) {
-  launch_persistent(k_xinv_b<T>, a, kLineThreads, lds, a.total, s);
+void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, int nthreads, size_t lds, hipStream_t s) {
+  if (nthreads == kXInvThreads)
+    launch_persistent(k_xinv_b<T, kXInvThreads>, a, kXInvThreads, lds, a.total, s);
+  else
+    launch_persistent(k_xinv_b<T, kLineThreads>, a, kLineThreads, lds, a.total, s);
 }
 
 
@@ -721,7 +730,7 @@ void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, size_t lds, hipStream_
   template void launch_zpush_batch<T>(const BatchArgs<ZPushParams<T>>&, int, size_t, hipStream_t);
 #define PSATD_INST_5(T)                                                                     \
   template void launch_xinv<T>(const XInvParams<T>&, hipStream_t);                          \
-  template void launch_xinv_batch<T>(const BatchArgs<XInvParams<T>>&, size_t, hipStream_t); \
+  template void launch_xinv_batch<T>(const BatchArgs<XInvParams<T>>&, int, size_t, hipStream_t); \
   template size_t xinv_lds<T>(const XInvParams<T>&);
 #define PSATD_CAT2(a, b) a##b
 #define PSATD_CAT(a, b) PSATD_CAT2(a, b)

@@ -237,6 +237,7 @@ struct psatd_plan {
   int ty1 = 0;       // real y-lines per P1 tile
   bool xtab = false; // P1 tiles leave LDS room for the gather table
   int ty5 = 0;       // real y-lines per P5 tile
+  int x5threads = 0; // P5 block size
   int nl_y = 0;      // lines per P2/P4 tile
   int zthreads = 0;  // threads of the P3 block
   int zcols = 0;     // (kx, ky) columns per P3 tile
@@ -301,6 +302,14 @@ int validate(const psatd_plan_desc* d) {
 // lines for short ones (many small boxes), always within LDS and the
 // one-butterfly-round-per-radix register budget checked by fit_lines.
 int x_line_cap(int n) { return std::max(8, 4608 / n); }   // complex x-lines (pairs of real lines)
+// P5 block size and real y-lines per P5 tile: the lines of a P1 tile of ty1
+// lines, as far as the butterfly budget of the smaller P5 block allows; the
+// P1 block size and tile when not even one line fits it.
+int x_inv_tile(psatd_plan* p, const LineSchedule& s, int em, size_t cs, int ty1, size_t lds) {
+  const int f = fit_lines(s, kXInvThreads, em, cs, x_line_cap(p->NX), lds);
+  p->x5threads = f >= 1 ? kXInvThreads : kLineThreads;
+  return f >= 1 ? 2 * std::min(ty1 / 2, f) : ty1;
+}
 // LDS of the P1 gather table for a box of NX cells along x: one int per column and per real row
 // of the largest tile, rounded to 16 bytes.
 size_t x_table_bytes(int NX) { return ((size_t)(NX + 2 * x_line_cap(NX)) * 4 + 15) & ~(size_t)15; }
@@ -365,7 +374,7 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   p->xtab = nc1 >= 1;
   if (!p->xtab) nc1 = fit_lines(sxs, nth, em, cs, x_line_cap(p->NX), lds_small);
   p->ty1 = 2 * std::max(nc1, 0);
-  p->ty5 = p->ty1;
+  p->ty5 = x_inv_tile(p, sxs, em, cs, p->ty1, lds_small);
   p->nl_y = fit_lines(sys, nth, em, cs, y_line_cap(p->NY), lds_small);
   choose_z_tile(p, szs, em, cs);
   if (p->ty1 <= 0 || p->ty5 <= 0 || p->nl_y <= 0 || p->zthreads == 0) {
@@ -621,10 +630,7 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
     x5.fd_GY = make_fastdiv(io.GY);
     x5.fd_GZ = make_fastdiv(io.GZ);
   }
-  x5.ld_drow = nth / (x5.ty / 2);
-  x5.ld_dcol = nth % (x5.ty / 2);
-  x5.wr_drow = nth / NX;
-  x5.wr_dcol = nth % NX;
+  x5.nthreads = p->x5threads;
   x5.fft = line_fft<T>(p->ax);
 }
 
@@ -834,7 +840,7 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
         if (t <= 0) continue;
         if (a == 0) {
           p->ty1 = t;
-          p->ty5 = t;
+          p->ty5 = x_inv_tile(p, A.sch, em, cs, t, lds_small);
         } else if (a == 1) {
           p->nl_y = t;
         } else {
@@ -852,7 +858,7 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
     launch_twiddles(A.tw, A.sch, p->fp64, s);
     if (a == 0) {
       p->ty1 = best_e.tile;
-      p->ty5 = best_e.tile;
+      p->ty5 = x_inv_tile(p, A.sch, em, cs, best_e.tile, lds_small);
     } else if (a == 1) {
       p->nl_y = best_e.tile;
     } else {
@@ -1016,7 +1022,11 @@ void enqueue_batch_step(const psatd_batch* b, hipStream_t s) {
   launch_ypass_batch<T>(batch_args<YPassParams<T>>(b, 1), 0, b->lds[1], s);
   launch_zpush_batch<T>(batch_args<ZPushParams<T>>(b, 2), b->zthreads, b->lds[2], s);
   launch_ypass_batch<T>(batch_args<YPassParams<T>>(b, 3), 1, b->lds[3], s);
-  launch_xinv_batch<T>(batch_args<XInvParams<T>>(b, 4), b->lds[4], s);
+  // one block size for all boxes: the larger one whenever a box needs it (a
+  // tile fitted for the smaller block also fits the larger)
+  int x5threads = kXInvThreads;
+  for (const psatd_plan* p : b->plans) x5threads = std::max(x5threads, p->x5threads);
+  launch_xinv_batch<T>(batch_args<XInvParams<T>>(b, 4), x5threads, b->lds[4], s);
 }
 
 int ensure_bound(psatd_batch* b, void* const* g1) {
