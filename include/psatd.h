@@ -29,8 +29,11 @@
  *     over the step; rho_old / rho_new are the charge densities at the start and
  *     at the end of the step.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = default
- *     stream) and return without synchronising.  A plan owns its workspace, so
- *     one plan must not run on two streams at once.
+ *     stream) and return without synchronising.  A plan (or batch) owns its
+ *     workspace, so one plan must not run on two streams at once: a step
+ *     called on a stream other than the previous step's, while that step is
+ *     still running, returns PSATD_ESTATE (checked with an event query; steps
+ *     enqueued on a stream under graph capture are not checked).
  *   - Return values: PSATD_OK or a negative PSATD_E* code; psatd_last_error()
  *     then returns a message for the calling thread.  Errors of kernels already
  *     in flight surface as PSATD_EHIP at a later call.
@@ -172,9 +175,11 @@ int psatd_plan_pass_times(psatd_plan* plan, double ms[5], long long* nsteps);
  *
  * subs[b] describes box b (interior sizes, guards, order); dx, dy, dz, dt, c,
  * eps0 and precision must agree across boxes.  origins[3*b .. 3*b+2] is the
- * global index of box b's first interior cell; gdims = {GX, GY, GZ}.  The
- * interiors are meant to tile G1 (not checked); every box interior must fit
- * in G1.  The batch owns a plan per box (tables and workspace). */
+ * global index of box b's first interior cell; gdims = {GX, GY, GZ}.  Every
+ * box interior must fit in G1, and no two interiors may share a G1 cell
+ * (periodic wrap included): PSATD_EINVAL otherwise, checked on the host before
+ * anything is allocated.  G1 cells outside every interior keep their values.
+ * The batch owns a plan per box (tables and workspace). */
 typedef struct psatd_batch psatd_batch;
 int psatd_batch_create(int nsub, const psatd_plan_desc* subs, const int* origins, const int gdims[3],
                        psatd_batch** out);
@@ -283,6 +288,27 @@ void psatd_mlp_destroy(psatd_mlp* mlp);
  * cost model; plans start from it and the autotuner may reorder or replace it.
  * Returns the number of stages, or PSATD_EINVAL / PSATD_EUNSUPPORTED. */
 int psatd_default_schedule(int n, int* radices, int max_radices, int* transform_len);
+
+/* ---------------------------------------------------------------- resources
+ * Device memory held by the library (plans, batches; not the surrogate
+ * network) is counted.  psatd_set_device_budget(bytes) caps it: an allocation
+ * that would pass the cap fails exactly like a failed hipMalloc, i.e. the
+ * constructor returns PSATD_ENOMEM and releases everything it had allocated.
+ * bytes < 0 removes the cap (the default).  Meant for callers that share the
+ * device with other work, and for testing the out-of-memory paths.  The cap is
+ * process-wide; it does not touch existing allocations. */
+int psatd_set_device_budget(long long bytes);
+/* Device bytes currently held by the library's plans and batches. */
+long long psatd_device_bytes_in_use(void);
+
+/* Reads an autotuner cache file (the format psatd_plan_autotune writes) into
+ * the process cache without a GPU.  An entry is accepted only if the file's
+ * schema version is this build's and its radices are compiled and multiply to
+ * the transform length named in its key; tiles are checked again against the
+ * plan's limits when an entry is used.  Reading stops at malformed text.
+ * *accepted / *rejected (either may be NULL) receive the counts.  A missing
+ * file is not an error (both counts 0). */
+int psatd_tune_cache_load(const char* path, int* accepted, int* rejected);
 
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char* psatd_last_error(void);

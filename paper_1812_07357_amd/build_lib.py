@@ -1,6 +1,6 @@
 """Build libpsatd.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1812_07357_amd.build_lib  (or build() from Python).
+Usage: python -m paper_1812_07357_amd.build_lib [--incremental]  (or build() from Python).
 Objects are compiled in parallel into _build/ and linked into
 paper_1812_07357_amd/libpsatd.so.
 """
@@ -50,11 +50,26 @@ def _compile(unit) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def _stale(unit) -> bool:
+    """True if the unit's object is missing or older than its source or any header."""
+    src, name, _ = unit
+    obj = os.path.join(BUILD, name + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    deps.append(os.path.join(ROOT, "include", "psatd.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every unit (or, with ``incremental``, only the stale ones) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    units = [u for u in SOURCES if not incremental or _stale(u)]
+    jobs = min(max(1, len(units)), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, units))
+    objs = [os.path.join(BUILD, name + ".o") for _, name, _ in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -67,4 +82,4 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv[1:])

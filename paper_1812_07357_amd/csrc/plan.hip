@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdlib>
 #include <functional>
 #include <map>
@@ -43,6 +44,29 @@ int check_hip(const char* where) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(PSATD_EHIP, "%s: %s", where, hipGetErrorString(e));
   return PSATD_OK;
+}
+
+// Device bytes the library holds (plans, batch descriptors) and an optional
+// ceiling on them (psatd_set_device_budget); a request that would pass the
+// ceiling fails as if hipMalloc had.
+std::atomic<long long> g_live_bytes{0};
+std::atomic<long long> g_budget{-1};
+
+hipError_t budget_malloc(void** out, size_t bytes) {
+  const long long b = g_budget.load();
+  if (b >= 0 && g_live_bytes.load() + (long long)bytes > b) {
+    *out = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  const hipError_t e = hipMalloc(out, bytes);
+  if (e == hipSuccess) g_live_bytes += (long long)bytes;
+  return e;
+}
+
+void budget_free(void* q, size_t bytes) {
+  if (!q) return;
+  (void)hipFree(q);
+  g_live_bytes -= (long long)bytes;
 }
 
 // LDS a single workgroup may use on the current device (160 KB per workgroup on
@@ -247,8 +271,14 @@ struct psatd_plan {
   void* wsA = nullptr;   // 11 * npts complex
   void* wsB = nullptr;   // 11 * npts complex
   size_t bytes = 0;
+  std::vector<std::pair<void*, size_t>> allocs;  // every device allocation of the plan
   int timing = 0;
   std::vector<std::array<hipEvent_t, 6>> events;  // per recorded step
+  // Completion of the last step and the stream it ran on: a step on another
+  // stream while that one is still in flight would share the workspace.
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool in_flight_known = false;
 };
 
 namespace {
@@ -263,19 +293,18 @@ void release_events(psatd_plan* p) {
 void free_plan(psatd_plan* p) {
   if (!p) return;
   release_events(p);
-  void* ptrs[] = {p->ax.tw, p->ax.chirp, p->ax.filt, p->ay.tw, p->ay.chirp, p->ay.filt, p->az.tw, p->az.chirp,
-                  p->az.filt, p->kd, p->kw, p->coef, p->wsA, p->wsB};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+  if (p->done) (void)hipEventDestroy(p->done);
+  for (const auto& a : p->allocs) budget_free(a.first, a.second);
   delete p;
 }
 
 int dalloc(psatd_plan* p, void** out, size_t bytes) {
-  if (hipMalloc(out, bytes) != hipSuccess) {
+  if (budget_malloc(out, bytes) != hipSuccess) {
     (void)hipGetLastError();
     *out = nullptr;
     return fail(PSATD_ENOMEM, "device allocation of %zu bytes failed", bytes);
   }
+  p->allocs.push_back({*out, bytes});
   p->bytes += bytes;
   return PSATD_OK;
 }
@@ -661,8 +690,56 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
   return check_hip("step kernels");
 }
 
+// Streams: an object (plan or batch) owns its workspace, so a step may start on
+// a stream other than the previous step's only once that step has finished.
+// Each step records an event at its end; a call on another stream queries it.
+// Steps enqueued while the stream is being captured into a graph are left to
+// the caller (an event query is not allowed there, and the graph runs later).
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+struct StreamGuard {
+  hipEvent_t* done;
+  hipStream_t* last;
+  bool* known;
+  // PSATD_ESTATE while the previous step runs on another stream.
+  int check(hipStream_t s, const char* what) const {
+    if (!*known || *last == s || capturing(s)) return PSATD_OK;
+    const hipError_t e = hipEventQuery(*done);
+    if (e == hipErrorNotReady)
+      return fail(PSATD_ESTATE, "%s: the previous step is still running on another stream", what);
+    if (e != hipSuccess) return check_hip(what);
+    return PSATD_OK;
+  }
+  // Records the end of the step just enqueued on s.
+  int mark(hipStream_t s, const char* what) const {
+    if (capturing(s)) return PSATD_OK;
+    if (!*done && hipEventCreateWithFlags(done, hipEventDisableTiming) != hipSuccess) {
+      *done = nullptr;
+      return check_hip(what);
+    }
+    if (hipEventRecord(*done, s) != hipSuccess) return check_hip(what);
+    *last = s;
+    *known = true;
+    return PSATD_OK;
+  }
+};
+
+StreamGuard guard_of(psatd_plan* p) { return StreamGuard{&p->done, &p->last_stream, &p->in_flight_known}; }
+
 int dispatch_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
-  return p->fp64 ? run_step<double>(p, io, s) : run_step<float>(p, io, s);
+  const StreamGuard g = guard_of(p);
+  int rc = g.check(s, "step");
+  if (rc) return rc;
+  rc = p->fp64 ? run_step<double>(p, io, s) : run_step<float>(p, io, s);
+  if (rc) return rc;
+  return g.mark(s, "step");
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -702,45 +779,140 @@ std::map<std::string, TuneEntry>& tune_cache() {
   return c;
 }
 
-void load_tune_file(const char* path) {
+// Version of the cache file format and of the schedule space it describes (the
+// compiled radices, tile rules and register budget).  Entries of files written
+// under another version are discarded.
+constexpr int kTuneSchema = 2;
+
+bool compiled_radix(int r) {
+  for (int k : kRadix)
+    if (k == r) return true;
+  return false;
+}
+
+// A radix sequence is usable for a transform of length m when its radices are all
+// compiled and multiply to m.
+bool valid_radices(const std::vector<int>& r, int m) {
+  if (m < 1 || (int)r.size() > kMaxStages || (m > 1 && r.empty())) return false;
+  long long prod = 1;
+  for (int v : r) {
+    if (!compiled_radix(v)) return false;
+    prod *= v;
+    if (prod > m) return false;
+  }
+  return prod == m;
+}
+
+// Minimal reader of the cache file written by save_tune_file:
+//   {"psatd_tune_cache": <schema>, "entries": {"<key>": {"radix": [..], "tile": <int>}, ...}}
+// Malformed text ends the scan; entries that fail the checks are counted as rejected.
+struct Scanner {
+  const std::string& t;
+  size_t i = 0;
+  void ws() {
+    while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\t' || t[i] == '\r')) ++i;
+  }
+  bool eat(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string* out) {
+    ws();
+    if (i >= t.size() || t[i] != '"') return false;
+    const size_t e = t.find('"', i + 1);
+    if (e == std::string::npos) return false;
+    *out = t.substr(i + 1, e - i - 1);
+    i = e + 1;
+    return true;
+  }
+  bool num(long long* out) {
+    ws();
+    size_t j = i;
+    if (j < t.size() && t[j] == '-') ++j;
+    const size_t d0 = j;
+    while (j < t.size() && t[j] >= '0' && t[j] <= '9' && j - d0 < 12) ++j;
+    if (j == d0 || (j < t.size() && t[j] >= '0' && t[j] <= '9')) return false;
+    *out = std::strtoll(t.c_str() + i, nullptr, 10);
+    i = j;
+    return true;
+  }
+};
+
+// Transform length m recorded in a cache key ("...|m=<m>|...").
+int key_length(const std::string& key) {
+  const size_t k = key.find("|m=");
+  if (k == std::string::npos) return -1;
+  long long v = 0;
+  size_t j = k + 3, d0 = j;
+  while (j < key.size() && key[j] >= '0' && key[j] <= '9' && j - d0 < 9) v = 10 * v + (key[j++] - '0');
+  return j == d0 ? -1 : (int)v;
+}
+
+void load_tune_file(const char* path, int* accepted = nullptr, int* rejected = nullptr) {
+  int ok = 0, bad = 0;
+  if (accepted) *accepted = 0;
+  if (rejected) *rejected = 0;
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   std::string text;
   char buf[4096];
   size_t k;
-  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 24)) text.append(buf, k);
   std::fclose(f);
-  // entries look like  "key": {"radix": [16, 4, 5], "tile": 16}
-  size_t pos = 0;
-  while ((pos = text.find("\"radix\"", pos)) != std::string::npos) {
-    const size_t kend = text.rfind('"', text.rfind(':', pos) - 1);
-    const size_t kbeg = text.rfind('"', kend - 1);
-    const std::string key = text.substr(kbeg + 1, kend - kbeg - 1);
-    TuneEntry e;
-    size_t lb = text.find('[', pos), rb = text.find(']', lb);
-    std::string list = text.substr(lb + 1, rb - lb - 1);
-    for (char& ch : list)
-      if (ch == ',') ch = ' ';
-    char* endp = &list[0];
-    for (;;) {
-      char* q = endp;
-      long v = std::strtol(q, &endp, 10);
-      if (endp == q) break;
-      e.radix.push_back((int)v);
-    }
-    const size_t tp = text.find("\"tile\"", rb);
-    e.tile = std::atoi(text.c_str() + text.find(':', tp) + 1);
-    tune_cache()[key] = e;
-    pos = rb;
+  Scanner sc{text};
+  std::string name;
+  long long schema = -1;
+  if (!sc.eat('{') || !sc.str(&name) || name != "psatd_tune_cache" || !sc.eat(':') || !sc.num(&schema) ||
+      !sc.eat(',') || !sc.str(&name) || name != "entries" || !sc.eat(':') || !sc.eat('{')) {
+    if (rejected) *rejected = 1;
+    return;
   }
+  const bool current = schema == kTuneSchema;
+  for (bool first = true;; first = false) {
+    if (sc.eat('}')) break;
+    if (!first && !sc.eat(',')) {
+      ++bad;
+      break;
+    }
+    std::string key, field;
+    TuneEntry e;
+    long long v = 0;
+    bool good = sc.str(&key) && sc.eat(':') && sc.eat('{') && sc.str(&field) && field == "radix" && sc.eat(':') &&
+                sc.eat('[');
+    if (good && !sc.eat(']')) {
+      do {
+        good = sc.num(&v) && v > 0 && v < 1000 && e.radix.size() < (size_t)kMaxStages;
+        if (good) e.radix.push_back((int)v);
+      } while (good && sc.eat(','));
+      good = good && sc.eat(']');
+    }
+    good = good && sc.eat(',') && sc.str(&field) && field == "tile" && sc.eat(':') && sc.num(&v) && sc.eat('}');
+    if (!good) {  // malformed: stop reading
+      ++bad;
+      break;
+    }
+    e.tile = (int)std::max(-1LL, std::min(v, 1LL << 20));
+    if (current && e.tile > 0 && valid_radices(e.radix, key_length(key))) {
+      tune_cache()[key] = e;
+      ++ok;
+    } else {
+      ++bad;
+    }
+  }
+  if (accepted) *accepted = ok;
+  if (rejected) *rejected = bad;
 }
 
 void save_tune_file(const char* path) {
   if (!path) return;
   FILE* f = std::fopen(path, "w");
   if (!f) return;
-  std::fprintf(f, "{\n  \"psatd_tune_cache\": 1,\n  \"entries\": {\n");
+  std::fprintf(f, "{\n  \"psatd_tune_cache\": %d,\n  \"entries\": {\n", kTuneSchema);
   size_t i = 0;
   for (auto& kv : tune_cache()) {
     std::fprintf(f, "    \"%s\": {\"radix\": [", kv.first.c_str());
@@ -808,9 +980,44 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
     char key[160];
     std::snprintf(key, sizeof key, "%s|%c|n=%d|m=%d|other=%dx%d", p->fp64 ? "fp64" : "fp32", "xyz"[a], A.n,
                   A.sch.n, lens[(a + 1) % 3], lens[(a + 2) % 3]);
+    // Tile sizes this build allows for a schedule of axis a (largest first, at most two),
+    // and whether a given tile is one of the allowed ones.
+    auto tile_limit = [&](const LineSchedule& sch) {
+      if (a == 0)
+        return fit_lines(sch, nth, em, cs, x_line_cap(p->NX), lds_small - (p->xtab ? x_table_bytes(p->NX) : 0));
+      return fit_lines(sch, nth, em, cs, y_line_cap(p->NY), lds_small);
+    };
+    auto tiles_for = [&](const LineSchedule& sch) {
+      std::vector<int> tl;
+      if (a == 2) {
+        for (int zt : kZThreads)
+          if (z_fits(sch, zt, em, cs, p->zcols) && tl.size() < 2) tl.push_back(zt);
+      } else {
+        for (int t = tile_limit(sch); t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(a == 0 ? 2 * t : t);
+      }
+      return tl;
+    };
+    auto tile_fits = [&](const LineSchedule& sch, int t) {
+      if (a == 2) return (t == kZThreads[0] || t == kZThreads[1]) && z_fits(sch, t, em, cs, p->zcols);
+      const int hi = tile_limit(sch);
+      return a == 0 ? (t >= 2 && t % 2 == 0 && t / 2 <= hi) : (t >= 1 && t <= hi);
+    };
+    // A cached entry is used only if it still describes a valid schedule of this
+    // plan under the current limits; otherwise it is dropped and the axis re-tuned.
     auto hit = tune_cache().find(key);
+    if (hit != tune_cache().end()) {
+      bool ok = valid_radices(hit->second.radix, A.sch.n);
+      if (ok) {
+        LineSchedule probe = A.sch;
+        set_radices(&probe, hit->second.radix);
+        ok = tile_fits(probe, hit->second.tile);
+      }
+      if (!ok) {
+        tune_cache().erase(hit);
+        hit = tune_cache().end();
+      }
+    }
     std::vector<std::vector<int>> cands;
-    std::vector<int> tiles;
     if (hit != tune_cache().end()) {
       cands.push_back(hit->second.radix);
     } else {
@@ -823,19 +1030,7 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
     for (auto& r : cands) {
       set_radices(&A.sch, r);
       launch_twiddles(A.tw, A.sch, p->fp64, s);
-      std::vector<int> tl;
-      if (a == 0) {
-        const int hi =
-            fit_lines(A.sch, nth, em, cs, x_line_cap(p->NX), lds_small - (p->xtab ? x_table_bytes(p->NX) : 0));
-        for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(2 * t);
-      } else if (a == 1) {
-        const int hi = fit_lines(A.sch, nth, em, cs, y_line_cap(p->NY), lds_small);
-        for (int t = hi; t >= 1 && tl.size() < 2; t = t / 2) tl.push_back(t);
-      } else {
-        for (int zt : kZThreads)
-          if (z_fits(A.sch, zt, em, cs, p->zcols) && tl.size() < 2) tl.push_back(zt);
-      }
-      if (hit != tune_cache().end()) tl = {hit->second.tile};
+      std::vector<int> tl = hit != tune_cache().end() ? std::vector<int>{hit->second.tile} : tiles_for(A.sch);
       for (int t : tl) {
         if (t <= 0) continue;
         if (a == 0) {
@@ -930,7 +1125,12 @@ struct psatd_batch {
   std::vector<psatd_plan*> plans;
   std::vector<std::array<int, 3>> origins;
   void* descs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per-pass parameter arrays
+  size_t desc_bytes[5] = {0, 0, 0, 0, 0};
   int* starts = nullptr;                                           // 5 x (nsub + 1) tile offsets
+  size_t starts_bytes = 0;
+  hipEvent_t done = nullptr;  // completion of the last step / replay (see psatd_plan::done)
+  hipStream_t last_stream = nullptr;
+  bool in_flight_known = false;
   int totals[5] = {0, 0, 0, 0, 0};
   size_t lds[5] = {0, 0, 0, 0, 0};
   int zthreads = 0;
@@ -950,22 +1150,24 @@ void free_batch(psatd_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  for (void* d : b->descs)
-    if (d) (void)hipFree(d);
-  if (b->starts) (void)hipFree(b->starts);
+  for (int k = 0; k < 5; ++k) budget_free(b->descs[k], b->desc_bytes[k]);
+  budget_free(b->starts, b->starts_bytes);
+  if (b->done) (void)hipEventDestroy(b->done);
   for (psatd_plan* p : b->plans) free_plan(p);
   delete b;
 }
 
 template <typename P>
-int upload(const std::vector<P>& v, void** dst) {
-  if (*dst) (void)hipFree(*dst);
+int upload(const std::vector<P>& v, void** dst, size_t* dst_bytes) {
+  budget_free(*dst, *dst_bytes);
   *dst = nullptr;
-  if (hipMalloc(dst, v.size() * sizeof(P)) != hipSuccess) {
+  *dst_bytes = 0;
+  if (budget_malloc(dst, v.size() * sizeof(P)) != hipSuccess) {
     (void)hipGetLastError();
     *dst = nullptr;
     return fail(PSATD_ENOMEM, "batch descriptor allocation failed");
   }
+  *dst_bytes = v.size() * sizeof(P);
   if (hipMemcpy(*dst, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice) != hipSuccess)
     return check_hip("batch descriptor upload");
   return PSATD_OK;
@@ -1000,12 +1202,14 @@ int bind_batch(psatd_batch* b, void* const* g1) {
   }
   for (int k = 0; k < 5; ++k) b->totals[k] = starts[k * (b->nsub + 1) + b->nsub];
   int rc;
-  if ((rc = upload(x1, &b->descs[0])) || (rc = upload(y2, &b->descs[1])) || (rc = upload(z3, &b->descs[2])) ||
-      (rc = upload(y4, &b->descs[3])) || (rc = upload(x5, &b->descs[4])))
+  if ((rc = upload(x1, &b->descs[0], &b->desc_bytes[0])) || (rc = upload(y2, &b->descs[1], &b->desc_bytes[1])) ||
+      (rc = upload(z3, &b->descs[2], &b->desc_bytes[2])) || (rc = upload(y4, &b->descs[3], &b->desc_bytes[3])) ||
+      (rc = upload(x5, &b->descs[4], &b->desc_bytes[4])))
     return rc;
   void* st = b->starts;
-  if ((rc = upload(starts, &st))) return rc;
+  rc = upload(starts, &st, &b->starts_bytes);
   b->starts = (int*)st;
+  if (rc) return rc;
   for (int f = 0; f < 11; ++f) b->bound[f] = g1[f];
   b->is_bound = true;
   return PSATD_OK;
@@ -1129,8 +1333,23 @@ int psatd_plan_tables(const psatd_plan* p, void* dst, void* stream) {
   return PSATD_OK;
 }
 
+int psatd_set_device_budget(long long bytes) {
+  g_budget.store(bytes < 0 ? -1 : bytes);
+  return PSATD_OK;
+}
+
+long long psatd_device_bytes_in_use(void) { return g_live_bytes.load(); }
+
+int psatd_tune_cache_load(const char* path, int* accepted, int* rejected) {
+  if (!path) return fail(PSATD_EINVAL, "NULL path");
+  load_tune_file(path, accepted, rejected);
+  return PSATD_OK;
+}
+
 int psatd_plan_autotune(psatd_plan* p, const char* cache_path, void* stream) {
   if (!p) return fail(PSATD_EINVAL, "NULL plan");
+  const int grc = guard_of(p).check((hipStream_t)stream, "psatd_plan_autotune");
+  if (grc) return grc;
   load_tune_file(cache_path);
   const int rc = p->fp64 ? autotune_plan<double>(p, (hipStream_t)stream) : autotune_plan<float>(p, (hipStream_t)stream);
   if (rc == PSATD_OK) save_tune_file(cache_path);
@@ -1277,6 +1496,28 @@ int psatd_batch_create(int nsub, const psatd_plan_desc* subs, const int* origins
         a.eps0 != c.eps0)
       return fail(PSATD_EINVAL, "box %d: precision, cell size, dt, c and eps0 must agree across the batch", i);
   }
+  // Every box writes its interior back to G1 in the last pass of a step, while other
+  // boxes of the same launch still run: two interiors sharing a G1 cell would race.
+  for (int i = 0; i < nsub; ++i) {
+    const int ni[3] = {subs[i].nx, subs[i].ny, subs[i].nz};
+    for (int a = 0; a < 3; ++a)
+      if (gdims[a] <= 0 || origins[3 * i + a] < 0 || origins[3 * i + a] >= gdims[a] || ni[a] <= 0 || ni[a] > gdims[a])
+        return fail(PSATD_EINVAL, "box %d: interior must be non-empty, no larger than the grid, origin in [0, gdims)",
+                    i);
+  }
+  for (int i = 0; i < nsub; ++i)
+    for (int j = i + 1; j < nsub; ++j) {
+      const int ni[3] = {subs[i].nx, subs[i].ny, subs[i].nz}, nj[3] = {subs[j].nx, subs[j].ny, subs[j].nz};
+      bool all = true;
+      for (int a = 0; a < 3 && all; ++a) {
+        // periodic intervals [oi, oi + ni) and [oj, oj + nj) modulo G intersect
+        const int G = gdims[a];
+        const int dij = ((origins[3 * j + a] - origins[3 * i + a]) % G + G) % G;
+        const int dji = ((origins[3 * i + a] - origins[3 * j + a]) % G + G) % G;
+        all = dij < ni[a] || dji < nj[a];
+      }
+      if (all) return fail(PSATD_EINVAL, "boxes %d and %d: interiors overlap on the global grid", i, j);
+    }
   psatd_batch* b = new psatd_batch;
   b->nsub = nsub;
   b->fp64 = subs[0].precision == PSATD_FP64;
@@ -1302,22 +1543,30 @@ int psatd_batch_create(int nsub, const psatd_plan_desc* subs, const int* origins
 
 int psatd_batch_step(psatd_batch* b, void* const* g1, void* stream) {
   if (!b) return fail(PSATD_EINVAL, "NULL batch");
-  int rc = ensure_bound(b, g1);
-  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
+  const StreamGuard g{&b->done, &b->last_stream, &b->in_flight_known};
+  int rc = g.check(s, "psatd_batch_step");
+  if (rc) return rc;
+  rc = ensure_bound(b, g1);
+  if (rc) return rc;
   if (b->fp64)
     enqueue_batch_step<double>(b, s);
   else
     enqueue_batch_step<float>(b, s);
-  return check_hip("psatd_batch_step");
+  rc = check_hip("psatd_batch_step");
+  if (rc) return rc;
+  return g.mark(s, "psatd_batch_step");
 }
 
 int psatd_batch_run(psatd_batch* b, void* const* g1, int nsteps, void* stream) {
   if (!b) return fail(PSATD_EINVAL, "NULL batch");
   if (nsteps < 1) return fail(PSATD_EINVAL, "nsteps must be >= 1");
-  int rc = ensure_bound(b, g1);
-  if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
+  const StreamGuard g{&b->done, &b->last_stream, &b->in_flight_known};
+  int rc = g.check(s, "psatd_batch_run");
+  if (rc) return rc;
+  rc = ensure_bound(b, g1);
+  if (rc) return rc;
   if (!b->exec || b->graph_steps != nsteps) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1345,7 +1594,7 @@ int psatd_batch_run(psatd_batch* b, void* const* g1, int nsteps, void* stream) {
     b->graph_steps = nsteps;
   }
   if (hipGraphLaunch(b->exec, s) != hipSuccess) return check_hip("graph launch");
-  return PSATD_OK;
+  return g.mark(s, "psatd_batch_run");
 }
 
 void psatd_batch_destroy(psatd_batch* b) { free_batch(b); }

@@ -117,6 +117,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_mlp_destroy.argtypes = [vp]
     lib.psatd_default_schedule.restype = cint
     lib.psatd_default_schedule.argtypes = [cint, ip, cint, ip]
+    lib.psatd_set_device_budget.restype = cint
+    lib.psatd_set_device_budget.argtypes = [ctypes.c_longlong]
+    lib.psatd_device_bytes_in_use.restype = ctypes.c_longlong
+    lib.psatd_device_bytes_in_use.argtypes = []
+    lib.psatd_tune_cache_load.restype = cint
+    lib.psatd_tune_cache_load.argtypes = [ctypes.c_char_p, ip, ip]
     lib.psatd_last_error.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     return lib
@@ -513,3 +519,20 @@ def default_schedule(n: int):
     ns = _lib.psatd_default_schedule(int(n), r, 16, ctypes.byref(m))
     _check(ns if ns < 0 else PSATD_OK)
     return [r[i] for i in range(ns)], m.value
+
+
+def set_device_budget(nbytes):
+    """Cap the device bytes the library's plans and batches may hold (None: no cap)."""
+    _check(_lib.psatd_set_device_budget(-1 if nbytes is None else int(nbytes)))
+
+
+def device_bytes_in_use() -> int:
+    """Device bytes currently held by the library's plans and batches."""
+    return int(_lib.psatd_device_bytes_in_use())
+
+
+def tune_cache_load(path):
+    """Read an autotuner cache file into the process cache (host only): (accepted, rejected) entries."""
+    a, r = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.psatd_tune_cache_load(os.fsencode(path), ctypes.byref(a), ctypes.byref(r)))
+    return int(a.value), int(r.value)

@@ -127,3 +127,77 @@ def test_default_schedule_rejects_bad_arguments(lib):
     m = ctypes.c_int()
     assert lib._lib.psatd_default_schedule(0, r, 4, ctypes.byref(m)) == lib.PSATD_EINVAL
     assert lib._lib.psatd_default_schedule(64, None, 4, ctypes.byref(m)) == lib.PSATD_EINVAL
+
+
+def _batch_create(lib, boxes, gdims):
+    descs = (lib.PlanDesc * len(boxes))()
+    origins = (ctypes.c_int * (3 * len(boxes)))()
+    for i, (o, n) in enumerate(boxes):
+        descs[i] = _desc(lib, nx=n[0], ny=n[1], nz=n[2])
+        for a in range(3):
+            origins[3 * i + a] = o[a]
+    h = ctypes.c_void_p()
+    rc = lib._lib.psatd_batch_create(len(boxes), descs, origins, (ctypes.c_int * 3)(*gdims), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("boxes", [
+    [((0, 0, 0), (8, 8, 8)), ((4, 0, 0), (8, 8, 8))],          # overlap along x, same y and z
+    [((0, 0, 0), (8, 8, 8)), ((12, 4, 6), (8, 8, 8))],         # wraps onto box 0 across the periodic edge
+    [((0, 0, 0), (16, 16, 16)), ((5, 5, 5), (1, 1, 1))],       # one cell inside another interior
+])
+def test_batch_rejects_overlapping_interiors_on_the_host(lib, boxes):
+    rc, h = _batch_create(lib, boxes, (16, 16, 16))
+    assert rc == lib.PSATD_EINVAL
+    assert "overlap" in lib._lib.psatd_last_error().decode()
+    assert h.value is None
+
+
+def test_batch_rejects_interiors_outside_the_grid(lib):
+    rc, h = _batch_create(lib, [((0, 0, 0), (8, 8, 8)), ((8, 0, 16), (8, 8, 8))], (16, 16, 16))
+    assert rc == lib.PSATD_EINVAL and h.value is None
+
+
+def test_device_budget_gives_enomem_and_leaks_nothing(lib):
+    """With a zero budget every constructor fails with ENOMEM before touching the device, and the
+    library holds no device memory afterwards (plan and batch cleanup paths)."""
+    before = lib.device_bytes_in_use()
+    lib.set_device_budget(0)
+    try:
+        h = ctypes.c_void_p()
+        assert lib._lib.psatd_plan_create_ex(ctypes.byref(_desc(lib)), ctypes.byref(h)) == lib.PSATD_ENOMEM
+        assert h.value is None
+        assert "allocation" in lib._lib.psatd_last_error().decode()
+        rc, hb = _batch_create(lib, [((0, 0, 0), (8, 8, 8)), ((8, 0, 0), (8, 8, 8))], (16, 8, 8))
+        assert rc == lib.PSATD_ENOMEM and hb.value is None
+        assert lib.device_bytes_in_use() == before
+    finally:
+        lib.set_device_budget(None)
+
+
+def _write_cache(path, body, schema=2):
+    path.write_text('{\n  "psatd_tune_cache": %d,\n  "entries": {\n%s\n  }\n}\n' % (schema, body))
+    return str(path)
+
+
+def test_tune_cache_reader_rejects_stale_and_corrupt_entries(lib, tmp_path):
+    good = '    "fp32|x|n=576|m=576|other=320x320": {"radix": [24, 24], "tile": 16}'
+    entries = [
+        good,
+        '    "fp32|y|n=320|m=320|other=320x576": {"radix": [16, 16], "tile": 16}',   # product 256 != 320
+        '    "fp32|z|n=19|m=19|other=8x8": {"radix": [19], "tile": 256}',           # radix 19 not compiled
+        '    "fp32|z|n=320|m=320|other=8x8": {"radix": [], "tile": 256}',           # empty schedule
+        '    "fp32|y|n=64|m=64|other=8x8": {"radix": [8, 8], "tile": -3}',          # bad tile
+        '    "fp32|y|n=64|len=64": {"radix": [8, 8], "tile": 4}',                    # key without a length
+    ]
+    assert lib.tune_cache_load(_write_cache(tmp_path / "a.json", ",\n".join(entries))) == (1, 5)
+    # another schema version: every entry is discarded
+    assert lib.tune_cache_load(_write_cache(tmp_path / "b.json", good, schema=1)) == (0, 1)
+    # malformed text: reading stops, nothing after the break is taken
+    bad = good + ',\n    "fp32|x|n=64|m=64|other=8x8": {"radix": [8, 8 "tile": 4}'
+    assert lib.tune_cache_load(_write_cache(tmp_path / "c.json", bad)) == (1, 1)
+    (tmp_path / "d.json").write_text("not json at all {{{")
+    assert lib.tune_cache_load(str(tmp_path / "d.json")) == (0, 1)
+    (tmp_path / "e.json").write_text("")
+    assert lib.tune_cache_load(str(tmp_path / "e.json")) == (0, 1)
+    assert lib.tune_cache_load(str(tmp_path / "missing.json")) == (0, 0)
