@@ -125,7 +125,8 @@ enum {
   PSATD_Q_BOX_X = 0, PSATD_Q_BOX_Y = 1, PSATD_Q_BOX_Z = 2,
   PSATD_Q_PRECISION = 3,
   PSATD_Q_WORKSPACE_BYTES = 4,  /* device bytes owned by the plan */
-  PSATD_Q_SPECTRUM_POINTS = 5   /* (box_x/2+1) * box_y * box_z */
+  PSATD_Q_SPECTRUM_POINTS = 5,  /* (box_x/2+1) * box_y * box_z */
+  PSATD_Q_Z_COLUMNS = 6         /* (kx, ky) columns per tile of the k-space pass */
 };
 int psatd_plan_query(const psatd_plan* plan, int what, long long* value);
 

@@ -458,6 +458,8 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
 
 // ---------------------------------------------------------------- the five passes
 struct StepIO {
+  void* wsA = nullptr;  // spectral workspaces (layouts A and B, 11 half spectra each)
+  void* wsB = nullptr;
   const void* src[11];  // P1 sources
   int gather;
   int GX, GY, GZ, x0, y0, z0;
@@ -507,8 +509,8 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   const long long npts = p->npts;
   const uint32_t fbytes = (uint32_t)(npts * (long long)sizeof(cx<T>));
   const int nth = kLineThreads;
-  cx<T>* A = (cx<T>*)p->wsA;
-  cx<T>* B = (cx<T>*)p->wsB;
+  cx<T>* A = (cx<T>*)io.wsA;
+  cx<T>* B = (cx<T>*)io.wsB;
   const T* kw = (const T*)p->kw;
 
   XFwdParams<T>& x1 = sp.x1;
@@ -928,6 +930,8 @@ void save_tune_file(const char* path) {
 template <typename T>
 float time_axis(psatd_plan* p, int ax, int reps, hipStream_t s) {
   StepIO io{};
+  io.wsA = p->wsA;
+  io.wsB = p->wsB;
   T* scratch = (T*)p->wsB;  // box-shaped real arrays for P1 inputs / P5 outputs
   for (int f = 0; f < 11; ++f) io.src[f] = scratch;
   for (int f = 0; f < 6; ++f) io.dst[f] = scratch;
@@ -1082,9 +1086,24 @@ int check_geometry(const psatd_plan* p, const int origin[3], const int gdims[3])
   return PSATD_OK;
 }
 
+// Argument checks shared by the fused steps on G1.
+int check_g1_call(const psatd_plan* p, void* const* g1, const int origin[3], const int gdims[3]) {
+  if (!p || !g1) return fail(PSATD_EINVAL, "NULL argument");
+  int rc = check_geometry(p, origin, gdims);
+  if (rc) return rc;
+  for (int f = 0; f < 11; ++f)
+    if (!g1[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
+  if (!distinct(g1, 11)) return fail(PSATD_EINVAL, "field arrays must be distinct");
+  if ((double)gdims[0] * gdims[1] * gdims[2] * p->rsize >= 4294967296.0)
+    return fail(PSATD_EUNSUPPORTED, "global arrays of 4 GiB or more are not supported");
+  return PSATD_OK;
+}
+
 // Inputs / outputs of a fused step on G1: gather with wrap, scatter of the interior.
 StepIO g1_io(const psatd_plan* p, void* const* g1, const int origin[3], const int gdims[3]) {
   StepIO io{};
+  io.wsA = p->wsA;
+  io.wsB = p->wsB;
   for (int f = 0; f < 11; ++f) io.src[f] = g1[f];
   for (int f = 0; f < 6; ++f) io.dst[f] = g1[f];
   io.gather = 1;
@@ -1317,6 +1336,7 @@ int psatd_plan_query(const psatd_plan* p, int what, long long* value) {
     case PSATD_Q_PRECISION: *value = p->d.precision; break;
     case PSATD_Q_WORKSPACE_BYTES: *value = (long long)p->bytes; break;
     case PSATD_Q_SPECTRUM_POINTS: *value = p->npts; break;
+    case PSATD_Q_Z_COLUMNS: *value = p->zcols; break;
     default: return fail(PSATD_EINVAL, "unknown query %d", what);
   }
   return PSATD_OK;
@@ -1348,6 +1368,7 @@ int psatd_tune_cache_load(const char* path, int* accepted, int* rejected) {
 
 int psatd_plan_autotune(psatd_plan* p, const char* cache_path, void* stream) {
   if (!p) return fail(PSATD_EINVAL, "NULL plan");
+  if (!p->wsA) return fail(PSATD_ESTATE, "psatd_plan_autotune: the plan was created without a workspace");
   const int grc = guard_of(p).check((hipStream_t)stream, "psatd_plan_autotune");
   if (grc) return grc;
   load_tune_file(cache_path);
@@ -1393,7 +1414,10 @@ int psatd_plan_pass_times(psatd_plan* p, double ms[5], long long* nsteps) {
 int psatd_push(psatd_plan* p, void* const E[3], void* const B[3], const void* const J[3], const void* rho_old,
                const void* rho_new, void* stream) {
   if (!p || !E || !B || !J) return fail(PSATD_EINVAL, "NULL argument");
+  if (!p->wsA) return fail(PSATD_ESTATE, "psatd_push: the plan was created without a workspace");
   StepIO io{};
+  io.wsA = p->wsA;
+  io.wsB = p->wsB;
   const void* all[11] = {E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2], rho_old, rho_new};
   for (int f = 0; f < 11; ++f) {
     if (!all[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
@@ -1416,38 +1440,10 @@ int psatd_push(psatd_plan* p, void* const E[3], void* const B[3], const void* co
 }
 
 int psatd_step_g1(psatd_plan* p, void* const* g1, const int origin[3], const int gdims[3], void* stream) {
-  if (!p || !g1) return fail(PSATD_EINVAL, "NULL argument");
-  int rc = check_geometry(p, origin, gdims);
+  int rc = check_g1_call(p, g1, origin, gdims);
   if (rc) return rc;
-  for (int f = 0; f < 11; ++f)
-    if (!g1[f]) return fail(PSATD_EINVAL, "field pointer %d is NULL", f);
-  if (!distinct(g1, 11)) return fail(PSATD_EINVAL, "field arrays must be distinct");
-  if ((double)gdims[0] * gdims[1] * gdims[2] * p->rsize >= 4294967296.0)
-    return fail(PSATD_EUNSUPPORTED, "global arrays of 4 GiB or more are not supported");
-  StepIO io{};
-  for (int f = 0; f < 11; ++f) io.src[f] = g1[f];
-  for (int f = 0; f < 6; ++f) io.dst[f] = g1[f];
-  io.gather = 1;
-  io.scatter = 1;
-  io.GX = gdims[0];
-  io.GY = gdims[1];
-  io.GZ = gdims[2];
-  const int g[3] = {p->d.ngx, p->d.ngy, p->d.ngz};
-  int st[3];
-  for (int a = 0; a < 3; ++a) st[a] = (int)((((long long)origin[a] - g[a]) % gdims[a] + gdims[a]) % gdims[a]);
-  io.x0 = st[0];
-  io.y0 = st[1];
-  io.z0 = st[2];
-  io.ox = origin[0];
-  io.oy = origin[1];
-  io.oz = origin[2];
-  io.src_elems = (long long)gdims[0] * gdims[1] * gdims[2];
-  io.dst_elems = io.src_elems;
-  io.y_lo = p->d.ngy;
-  io.y_hi = p->d.ngy + p->d.ny;
-  io.z_lo = p->d.ngz;
-  io.z_hi = p->d.ngz + p->d.nz;
-  return dispatch_step(p, io, (hipStream_t)stream);
+  if (!p->wsA) return fail(PSATD_ESTATE, "psatd_step_g1: the plan was created without a workspace");
+  return dispatch_step(p, g1_io(p, g1, origin, gdims), (hipStream_t)stream);
 }
 
 int guard_fill(psatd_plan* p, const void* const* g1, void* const* box, int nfields, const int origin[3],

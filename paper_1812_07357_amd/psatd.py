@@ -24,7 +24,7 @@ PSATD_ESTATE = -5
 PSATD_FP32 = 0
 PSATD_FP64 = 1
 
-Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS = range(6)
+Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS, Q_Z_COLUMNS = range(7)
 
 
 class PlanDesc(ctypes.Structure):
@@ -167,14 +167,15 @@ class Plan:
     triple; ``precision`` "fp32" or "fp64".
     """
 
-    def __init__(self, nx, ny, nz, nguard=0, order=0, dx=1.0, dt=0.5, c=1.0, eps0=1.0, precision="fp32"):
+    def __init__(self, nx, ny, nz, nguard=0, order=0, dx=1.0, dt=0.5, c=1.0, eps0=1.0, precision="fp32",
+                 flags=0):
         import torch
 
         g = _triple(nguard)
         d = _triple(dx)
         desc = PlanDesc(int(nx), int(ny), int(nz), int(g[0]), int(g[1]), int(g[2]), int(order),
                         float(d[0]), float(d[1]), float(d[2]), float(dt), float(c), float(eps0),
-                        PSATD_FP64 if precision == "fp64" else PSATD_FP32, 0)
+                        PSATD_FP64 if precision == "fp64" else PSATD_FP32, int(flags))
         h = ctypes.c_void_p()
         _check(_lib.psatd_plan_create_ex(ctypes.byref(desc), ctypes.byref(h)))
         self._h = h

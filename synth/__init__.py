@@ -20,4 +20,5 @@ from .fields import (  # noqa: F401
     laser_modes,
     macro_particle_deposit,
     uneven_decomposition,
+    plane_waves_and_blob,
 )

@@ -234,3 +234,31 @@ def uneven_decomposition(rng: np.random.Generator, per_axis: int = 4, smin: int 
                     "order": int(rng.choice(orders)),
                 })
     return gdims, boxes
+
+
+def plane_waves_and_blob(rng: np.random.Generator, shape, d: float, nmodes: int, mmax=None, sigma: float = 3.0,
+                         amplitude: float = 0.1, c: float = 1.0):
+    """(11, Nz, Ny, Nx) float64 arrays: ``nmodes`` vacuum plane waves in E, B plus a Gaussian current blob.
+
+    Modes as ``plane_wave_modes`` (amplitudes N(0, 1), random phases); the
+    polarisation is the part of a random unit vector orthogonal to the grid
+    wave vector k, and B = k-hat x E / c (forward propagation).  J is a centred
+    Gaussian blob of width ``sigma`` cells and peak ``amplitude`` along a seeded
+    unit direction, held constant in time; rho_old and rho_new are left zero
+    (whoever needs a charge consistent with J computes it).
+    """
+    nz, ny, nx = shape
+    pw = plane_wave_modes(rng, shape, nmodes, mmax=mmax)
+    dims = np.array([nx, ny, nz], dtype=np.float64)
+    ev, bv = [], []
+    for j in range(nmodes):
+        kvec = pw["m"][j] / dims
+        e = transverse_unit(pw["u"][j], kvec)
+        ev.append(e)
+        bv.append(np.cross(kvec / np.linalg.norm(kvec), e) / c)
+    out = np.zeros((11,) + tuple(shape))
+    out[0:3], out[3:6] = plane_wave_sum(shape, d, pw["m"], pw["amp"], pw["phase"], ev, bv)
+    direction = rng.normal(0.0, 1.0, size=3)
+    centre = tuple(0.5 * n * d for n in (nx, ny, nz))
+    out[6:9] = gaussian_blob(shape, d, centre, sigma, amplitude, direction)
+    return out

@@ -4,6 +4,12 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# The oracle's library FFTs may use the host's cores (its arithmetic is unchanged).
+try:
+    _ncpu = len(os.sched_getaffinity(0))
+except AttributeError:
+    _ncpu = os.cpu_count() or 1
+os.environ.setdefault("ORACLE_FFT_WORKERS", str(max(1, min(16, _ncpu))))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
