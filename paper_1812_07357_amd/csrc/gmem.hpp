@@ -44,6 +44,13 @@ struct gm<float> {
   static __device__ __forceinline__ void stc(rsrc_t r, uint32_t i, cx<float> v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0, 0);
   }
+  // complex element i at a further byte offset `so` held in a scalar register
+  static __device__ __forceinline__ cx<float> ldc_s(rsrc_t r, uint32_t i, uint32_t so) {
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, (int)so, 0));
+  }
+  static __device__ __forceinline__ void stc_s(rsrc_t r, uint32_t i, uint32_t so, cx<float> v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, (int)so, 0);
+  }
   // complex elements i and i + 1 in one 16-byte store
   static __device__ __forceinline__ void stc2(rsrc_t r, uint32_t i, cx<float> a, cx<float> b) {
     const u32x4 w = {__float_as_uint(a.re), __float_as_uint(a.im), __float_as_uint(b.re), __float_as_uint(b.im)};
@@ -68,6 +75,12 @@ struct gm<double> {
   static __device__ __forceinline__ void stc2(rsrc_t r, uint32_t i, cx<double> a, cx<double> b) {
     stc(r, i, a);
     stc(r, i + 1u, b);
+  }
+  static __device__ __forceinline__ cx<double> ldc_s(rsrc_t r, uint32_t i, uint32_t so) {
+    return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, i * 16u, (int)so, 0));
+  }
+  static __device__ __forceinline__ void stc_s(rsrc_t r, uint32_t i, uint32_t so, cx<double> v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, i * 16u, (int)so, 0);
   }
 };
 

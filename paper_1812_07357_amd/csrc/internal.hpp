@@ -62,6 +62,8 @@ struct YPassParams {
   int u_lo, u_hi;        // lines processed: [u_lo, u_hi)
   int utiles, nouter, ntiles;
   int p_lo, p_hi;        // output positions written: [p_lo, p_hi)
+  int ra, rb;            // two-stage kernel with compile-time radices (ra, rb) and
+                         // kYTwoStageLines lines per tile, or 0, 0
   FastDiv fd_utiles, fd_nouter, fd_n, fd_nl, fd_nl_last, fd_np;
   LineFFT<T> fft;
 };
@@ -82,6 +84,7 @@ struct ZPushParams {
   int zgroup;            // lines per transform call (the lines of a tile are transformed in groups)
   int ntiles;            // ceil(NXH * NY / ncol)
   int z_lo, z_hi;        // output z written: [z_lo, z_hi)
+  int ra, rb;            // two-stage kernel with compile-time radices (ra, rb), or 0, 0
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
   FastDiv fd_NY, fd_NZ, fd_ncol;
@@ -112,6 +115,24 @@ struct XInvParams {
                          // when a line's butterflies exceed the smaller block)
   LineFFT<T> fft;
 };
+
+// Line schedules (RA, RB), N = RA * RB, with a compiled two-stage z kernel
+// (single-column tiles of 256 threads, every offset a compile-time constant).
+constexpr int kZTwoStage[][2] = {{16, 20}, {20, 16}, {16, 16}, {24, 24}, {32, 17}, {17, 32}};
+constexpr int kZTwoStageThreads = 256;
+// LDS slots per line of the two-stage kernel: the intermediate rows of RB
+// butterflies padded to RA | 1 slots, or the N points in natural order.
+constexpr int two_stage_slots(int ra, int rb) { return ((rb * (ra | 1) > ra * rb) ? rb * (ra | 1) : ra * rb) | 1; }
+
+// Line schedules (RA, RB) with compiled two-stage y kernels, their lines per tile,
+// LDS slots per line (RB padded rows of RA | 1 slots) and block size (one
+// butterfly per thread in either stage).
+constexpr int kYTwoStage[][2] = {{16, 20}, {20, 16}, {16, 16}, {24, 24}, {32, 17}, {17, 32}};
+constexpr int kYTwoStageLines = 16;
+constexpr int two_stage_y_slots(int ra, int rb) { return (rb * (ra | 1)) | 1; }
+constexpr int two_stage_y_threads(int ra, int rb) {
+  return ((kYTwoStageLines * (ra > rb ? ra : rb) + 63) / 64) * 64;
+}
 
 // Threads per block of the x and y passes.
 constexpr int kLineThreads = 512;
@@ -164,6 +185,9 @@ template <typename T>
 void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s);
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s);
+// The two-stage z kernel for p.ra, p.rb (one of kZTwoStage).
+template <typename T>
+void launch_zpush_two_stage(const ZPushParams<T>& p, hipStream_t s);
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s);
 

@@ -298,6 +298,100 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
   }
 }
 
+// ------------------------------------------------------------------ P2 / P4, two-stage lines
+// The y passes for lines of N = RA * RB points with compile-time radices and
+// tiles of NL lines (the stage structure of the two-stage z kernel below):
+// stage A reads each butterfly's RA inputs straight from global memory into
+// registers and leaves its outputs in padded LDS rows; stage B reads columns
+// of those rows, applies the twiddles and writes its RB outputs straight to
+// global memory.  Lanes walk the contiguous direction of each side: along the
+// line where positions are contiguous (stride 1), across the tile's lines
+// where lines are (P2 writes, P4 reads consecutive z).  The strided offsets
+// of a butterfly's points are scalar (the same for every lane), so no lane
+// computes a per-point address.  P2 (S_ = -1) reads lines with contiguous
+// positions and writes consecutive lines contiguously; P4 (S_ = +1) the reverse.
+template <int RA, int RB, int NL>
+struct TwoStageY {
+  static constexpr int N = RA * RB;
+  static constexpr int PA = RA | 1;
+  static constexpr int LD = (RB * PA) | 1;
+  static constexpr int NA = NL * RB;  // stage A butterflies per tile
+  static constexpr int NB = NL * RA;  // stage B butterflies per tile
+};
+
+template <int S_, typename T, int RA, int RB, int NL, int NTH, typename Src>
+__device__ __forceinline__ void ypass_two_stage_body(const Src& S) {
+  using G = TwoStageY<RA, RB, NL>;
+  constexpr int PA = G::PA, LD = G::LD;
+  cx<T>* lds = lds_base<T>();
+  const int tid = threadIdx.x;
+  for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
+    int lt;
+    const YPassParams<T>& p = S.box(tile, lt);
+    const int q = fdiv(lt, p.fd_utiles);
+    const int ut = lt - q * p.utiles;
+    const int f = fdiv(q, p.fd_nouter);
+    const int o = q - f * p.nouter;
+    const int u0 = p.u_lo + ut * NL;
+    const int nlt = min(NL, p.u_hi - u0);
+    const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);
+    // stage A: global -> registers -> DFT -> padded rows
+    {
+      const rsrc_t in = make_rsrc(p.in + (i64)f * p.fs_in, p.in_bytes);
+      const uint32_t sstep = (uint32_t)(RB * p.ps_in * (int)sizeof(cx<T>));  // bytes between a butterfly's points
+#pragma unroll
+      for (int b0 = 0; b0 < G::NA; b0 += NTH) {
+        const int b = b0 + tid;
+        if (b0 + NTH <= G::NA || b < G::NA) {
+          const int line = S_ < 0 ? b / RB : b % NL;
+          const int j = S_ < 0 ? b - line * RB : b / NL;
+          const bool ok = line < nlt;
+          const uint32_t base = ok ? (uint32_t)(o * p.os_in + (u0 + line) * p.ls_in + j * p.ps_in) : kOOB;
+          cx<T> v[RA];
+#pragma unroll
+          for (int t = 0; t < RA; ++t) v[t] = gm<T>::ldc_s(in, base, (uint32_t)t * sstep);
+          dft<RA, S_, T>::run(v);
+          cx<T>* y = lds + line * LD + j * PA;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) y[t] = v[t];
+        }
+      }
+    }
+    __syncthreads();
+    // stage B: padded rows -> twiddles -> DFT -> global (positions [p_lo, p_hi))
+    {
+      const rsrc_t out = make_rsrc(p.out + (i64)f * p.fs_out, p.out_bytes);
+      const uint32_t sstep = (uint32_t)(RA * p.ps_out * (int)sizeof(cx<T>));
+#pragma unroll
+      for (int b0 = 0; b0 < G::NB; b0 += NTH) {
+        const int b = b0 + tid;
+        if (b0 + NTH <= G::NB || b < G::NB) {
+          const int line = S_ > 0 ? b / RA : b % NL;
+          const int k = S_ > 0 ? b - line * RA : b / NL;
+          const cx<T>* y = lds + line * LD + k;
+          cx<T> v[RB];
+#pragma unroll
+          for (int t = 0; t < RB; ++t) v[t] = y[t * PA];
+          const Tw<T>* w = twb + k * (RB - 1) - 1;
+          if (k > 0) {
+#pragma unroll
+            for (int t = 1; t < RB; ++t) v[t] = twmul<S_>(v[t], w[t]);
+          }
+          dft<RB, S_, T>::run(v);
+          const bool ok = line < nlt;
+          const uint32_t base = (uint32_t)(o * p.os_out + (u0 + line) * p.ls_out + k * p.ps_out);
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            const int pos = k + RA * t;
+            gm<T>::stc_s(out, (ok && pos >= p.p_lo && pos < p.p_hi) ? base : kOOB, (uint32_t)t * sstep, v[t]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ P3
 // Push (Sec. 1.1; J constant over the step, rho at both ends):
 //   E' = C E + i c^2 S1 (K x B) - (S1/eps0) J + i (c^2/eps0) K (X3 rho_old - X2 rho_new)
@@ -312,10 +406,10 @@ __device__ __forceinline__ void ypass_body(const Src& S) {
 // does not hold the next tile in registers: the transforms leave no room for
 // it, and small blocks with a 96-register cap (FP32, five per CU) let several
 // tiles per CU overlap each other's loads and barriers instead.
-// The push at one k-space point: column col (LDS lines of field f at
-// f * fs + cbase) and z index kz; k_x, k_y of the column given.
+// The push at one k-space point: column col, z index kz, its field-0 value at LDS
+// slot s and field f at s + f * fs; k_x, k_y of the column given.
 template <typename T>
-__device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, int fs, int cbase, int col, int kz,
+__device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int col, int kz,
                                            T kx, T ky) {
   const T c2 = p.c2, ie = p.inv_eps0;
   const uint32_t idx = (uint32_t)(col * p.NZ + kz);
@@ -324,7 +418,6 @@ __device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, 
   for (int k = 0; k < 5; ++k) cc[k] = gm<T>::ld(make_rsrc(p.coef + (i64)k * p.npts, p.coef_bytes), idx);
   const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
   const T kzz = p.kz[kz];
-  const int s = cbase + lpad(kz);
   const cx<T> ex = lds[0 * fs + s], ey = lds[1 * fs + s], ez = lds[2 * fs + s];
   const cx<T> bx = lds[3 * fs + s], by = lds[4 * fs + s], bz = lds[5 * fs + s];
   const cx<T> jx = lds[6 * fs + s], jy = lds[7 * fs + s], jz = lds[8 * fs + s];
@@ -417,7 +510,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
         const int kxi = fdiv(col, p.fd_NY);
         const int kyi = col - kxi * p.NY;
         const T kx = p.kx[kxi], ky = p.ky[kyi];
-        for (int kz = tid; kz < NZ; kz += nth) push_point(p, lds, fs, c * ld, col, kz, kx, ky);
+        for (int kz = tid; kz < NZ; kz += nth) push_point(p, lds, fs, c * ld + lpad(kz), col, kz, kx, ky);
       }
     } else {
       // short lines: (column, k_z) pairs spread over the block
@@ -427,7 +520,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
         const int col = col0 + c;
         const int kxi = fdiv(col, p.fd_NY);
         const int kyi = col - kxi * p.NY;
-        push_point(p, lds, fs, c * ld, col, kz, p.kx[kxi], p.ky[kyi]);
+        push_point(p, lds, fs, c * ld + lpad(kz), col, kz, p.kx[kxi], p.ky[kyi]);
       }
     }
     __syncthreads();
@@ -443,6 +536,154 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
       const rsrc_t rb = make_rsrc(p.b + (i64)f * p.npts, p.field_bytes);
       for (int z = p.z_lo + lane; z < p.z_hi; z += 64)
         gm<T>::stc(rb, (uint32_t)((col0 + c) * NZ + z), lds[l * ld + lpad(z)]);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ P3, two-stage lines
+// The same pass for z-lines of N = RA * RB points with both radices known at
+// compile time (one (kx, ky) column per tile).  Every LDS and global offset of a
+// butterfly is then a constant from one base address, and the lines go
+// straight from global memory into the registers of their first stage:
+//   stage A (radix RA, RB butterflies per line): butterfly j of a line takes
+//     x[j + RB t], t < RA, and its outputs go to the intermediate row j,
+//     Y[j][t] (rows padded to PA = RA | 1 slots so that the lanes' rows fall in
+//     different LDS banks);
+//   stage B (radix RB, RA butterflies per line): butterfly j' takes column j'
+//     of Y, Y[t'][j'] = y[j' + RA t'], applies w_N^(t' j'), and its outputs are
+//     the transform at j' + RA t (natural order).
+// The forward results of the 11 lines are written to LDS in natural order for
+// the push; the 6 lines of E and B then run stage A from LDS and stage B
+// straight to global memory (interior z only).
+template <int RA, int RB>
+struct TwoStage {
+  static constexpr int N = RA * RB;
+  static constexpr int PA = RA | 1;
+  static constexpr int LD = two_stage_slots(RA, RB);  // LDS slots per line
+};
+
+template <typename T, int RA, int RB, int NTH, typename Src>
+__device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
+  using G = TwoStage<RA, RB>;
+  constexpr int N = G::N, PA = G::PA, LD = G::LD;
+  cx<T>* lds = lds_base<T>();
+  const int tid = threadIdx.x;
+  for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
+    int col;
+    const ZPushParams<T>& p = S.box(tile, col);
+    const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);  // stage B twiddles of butterfly k at k (RB - 1)
+    // forward stage A: global -> registers -> DFT -> intermediate rows
+#pragma unroll
+    for (int b0 = 0; b0 < 11 * RB; b0 += NTH) {
+      const int b = b0 + tid;
+      if (b0 + NTH <= 11 * RB || b < 11 * RB) {
+        const int f = b / RB, j = b - f * RB;
+        // plain global addresses: the lanes of a wave read several fields, which a
+        // buffer resource (one base per wave) could only serve one field at a time
+        const cx<T>* src = p.b + (i64)f * p.npts + (i64)col * N + j;
+        cx<T> v[RA];
+#pragma unroll
+        for (int t = 0; t < RA; ++t) v[t] = src[RB * t];
+        dft<RA, -1, T>::run(v);
+        cx<T>* y = lds + f * LD + j * PA;
+#pragma unroll
+        for (int t = 0; t < RA; ++t) y[t] = v[t];
+      }
+    }
+    __syncthreads();
+    // forward stage B: intermediate columns -> twiddles -> DFT -> natural order (in place)
+    {
+      constexpr int NB = (11 * RA + NTH - 1) / NTH;
+      cx<T> v[NB][RB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int b = u * NTH + tid;
+        if (b < 11 * RA) {
+          const int f = b / RA, k = b - f * RA;
+          const cx<T>* y = lds + f * LD + k;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) v[u][t] = y[t * PA];
+          const Tw<T>* w = twb + k * (RB - 1) - 1;
+          if (k > 0) {
+#pragma unroll
+            for (int t = 1; t < RB; ++t) v[u][t] = twmul<-1>(v[u][t], w[t]);
+          }
+          dft<RB, -1, T>::run(v[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int b = u * NTH + tid;
+        if (b < 11 * RA) {
+          const int f = b / RA, k = b - f * RA;
+          cx<T>* z = lds + f * LD + k;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) z[t * RA] = v[u][t];
+        }
+      }
+    }
+    __syncthreads();
+    // push, point by point (natural order, field f of point kz at f * LD + kz)
+    {
+      const int kxi = fdiv(col, p.fd_NY);
+      const int kyi = col - kxi * p.NY;
+      const T kx = p.kx[kxi], ky = p.ky[kyi];
+      for (int kz = tid; kz < N; kz += NTH) push_point(p, lds, LD, kz, col, kz, kx, ky);
+    }
+    __syncthreads();
+    // inverse stage A on the 6 lines of E and B, from LDS (natural order) back to rows
+    {
+      constexpr int NA = (6 * RB + NTH - 1) / NTH;
+      cx<T> v[NA][RA];
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        const int b = u * NTH + tid;
+        if (b < 6 * RB) {
+          const int f = b / RB, j = b - f * RB;
+          const cx<T>* x = lds + f * LD + j;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) v[u][t] = x[RB * t];
+          dft<RA, 1, T>::run(v[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        const int b = u * NTH + tid;
+        if (b < 6 * RB) {
+          const int f = b / RB, j = b - f * RB;
+          cx<T>* y = lds + f * LD + j * PA;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) y[t] = v[u][t];
+        }
+      }
+    }
+    __syncthreads();
+    // inverse stage B: rows -> twiddles -> DFT -> global (interior z only)
+#pragma unroll
+    for (int b0 = 0; b0 < 6 * RA; b0 += NTH) {
+      const int b = b0 + tid;
+      if (b0 + NTH <= 6 * RA || b < 6 * RA) {
+        const int f = b / RA, k = b - f * RA;
+        const cx<T>* y = lds + f * LD + k;
+        cx<T> v[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) v[t] = y[t * PA];
+        const Tw<T>* w = twb + k * (RB - 1) - 1;
+        if (k > 0) {
+#pragma unroll
+          for (int t = 1; t < RB; ++t) v[t] = twmul<1>(v[t], w[t]);
+        }
+        dft<RB, 1, T>::run(v);
+        cx<T>* dst = p.b + (i64)f * p.npts + (i64)col * N + k;
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+          const int z = k + RA * t;
+          if (z >= p.z_lo && z < p.z_hi) dst[RA * t] = v[t];
+        }
+      }
     }
     __syncthreads();
   }
@@ -573,6 +814,13 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof
 k_zpush(ZPushParams<T>) {
   zpush_body<T, MULTI>(SingleSrc<ZPushParams<T>>{});
 }
+// Two-stage z kernel: three 4-wave blocks per CU in FP32 (168 registers hold a
+// stage's butterfly, its twiddles and the small-DFT temporaries without spills).
+template <typename T, int RA, int RB>
+__global__ void __launch_bounds__(kZTwoStageThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+k_zpush2(ZPushParams<T>) {
+  zpush_two_stage_body<T, RA, RB, kZTwoStageThreads>(SingleSrc<ZPushParams<T>>{});
+}
 template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_zpush_b(BatchArgs<ZPushParams<T>> a) {
@@ -580,6 +828,11 @@ k_zpush_b(BatchArgs<ZPushParams<T>> a) {
 }
 // x inverse: at most 128 registers in FP32; 256-thread blocks (four per CU) unless
 // the lines need the larger block.
+template <int S, typename T, int RA, int RB>
+__global__ void __launch_bounds__(two_stage_y_threads(RA, RB))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_ypass2(YPassParams<T>) {
+  ypass_two_stage_body<S, T, RA, RB, kYTwoStageLines, two_stage_y_threads(RA, RB)>(SingleSrc<YPassParams<T>>{});
+}
 template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 k_xinv(XInvParams<T>) {
@@ -656,8 +909,28 @@ template <typename T>
 void launch_xfwd(const XFwdParams<T>& p, hipStream_t s) {
   launch_persistent(k_xfwd<T>, p, kLineThreads, xfwd_lds(p), p.ntiles, s);
 }
+template <typename T, int I = 0>
+void launch_ypass_two_stage_at(const YPassParams<T>& p, int inverse, hipStream_t s) {
+  if constexpr (I < (int)(sizeof(kYTwoStage) / sizeof(kYTwoStage[0]))) {
+    constexpr int RA = kYTwoStage[I][0], RB = kYTwoStage[I][1];
+    if (p.ra == RA && p.rb == RB) {
+      const size_t lds = (size_t)kYTwoStageLines * two_stage_y_slots(RA, RB) * cx_bytes<T>();
+      constexpr int nth = two_stage_y_threads(RA, RB);
+      if (inverse)
+        launch_persistent(k_ypass2<1, T, RA, RB>, p, nth, lds, p.ntiles, s);
+      else
+        launch_persistent(k_ypass2<-1, T, RA, RB>, p, nth, lds, p.ntiles, s);
+      return;
+    }
+    launch_ypass_two_stage_at<T, I + 1>(p, inverse, s);
+  }
+}
 template <typename T>
 void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
+  if (p.ra > 0) {
+    launch_ypass_two_stage_at<T>(p, inverse, s);
+    return;
+  }
   if (inverse)
     launch_persistent(k_ypass<1, T>, p, kLineThreads, ypass_lds(p), p.ntiles, s);
   else
@@ -670,8 +943,33 @@ void launch_zpush_cols(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
   else
     launch_persistent(k_zpush<T, kZThreads[1], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
 }
+template <typename T, int I = 0>
+void launch_two_stage_at(const ZPushParams<T>& p, hipStream_t s) {
+  if constexpr (I < (int)(sizeof(kZTwoStage) / sizeof(kZTwoStage[0]))) {
+    constexpr int RA = kZTwoStage[I][0], RB = kZTwoStage[I][1];
+    if (p.ra == RA && p.rb == RB) {
+      const size_t lds = (size_t)11 * two_stage_slots(RA, RB) * cx_bytes<T>();
+      launch_persistent(k_zpush2<T, RA, RB>, p, kZTwoStageThreads, lds, p.ntiles, s);
+      return;
+    }
+    launch_two_stage_at<T, I + 1>(p, s);
+  }
+}
+template <typename T>
+void launch_zpush_two_stage(const ZPushParams<T>& p, hipStream_t s) {
+  launch_two_stage_at<T>(p, s);
+}
+// Built as a unit of its own (the two-stage kernels compile in parallel with the rest).
+#if defined(PSATD_UNIT) && PSATD_UNIT != 6
+extern template void launch_zpush_two_stage<float>(const ZPushParams<float>&, hipStream_t);
+extern template void launch_zpush_two_stage<double>(const ZPushParams<double>&, hipStream_t);
+#endif
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
+  if (p.ra > 0) {
+    launch_zpush_two_stage<T>(p, s);
+    return;
+  }
   if (p.ncol == 1)
     launch_zpush_cols<T, false>(p, nthreads, s);
   else
@@ -728,6 +1026,7 @@ void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, int nthreads, size_t l
   template size_t zpush_lds<T>(const ZPushParams<T>&);
 #define PSATD_INST_4(T) \
   template void launch_zpush_batch<T>(const BatchArgs<ZPushParams<T>>&, int, size_t, hipStream_t);
+#define PSATD_INST_6(T) template void launch_zpush_two_stage<T>(const ZPushParams<T>&, hipStream_t);
 #define PSATD_INST_5(T)                                                                     \
   template void launch_xinv<T>(const XInvParams<T>&, hipStream_t);                          \
   template void launch_xinv_batch<T>(const BatchArgs<XInvParams<T>>&, int, size_t, hipStream_t); \
@@ -737,7 +1036,8 @@ void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, int nthreads, size_t l
 #if defined(PSATD_UNIT) && defined(PSATD_REAL)
 PSATD_CAT(PSATD_INST_, PSATD_UNIT)(PSATD_REAL)
 #else
-#define PSATD_INST_ALL(T) PSATD_INST_1(T) PSATD_INST_2(T) PSATD_INST_3(T) PSATD_INST_4(T) PSATD_INST_5(T)
+#define PSATD_INST_ALL(T) \
+  PSATD_INST_1(T) PSATD_INST_2(T) PSATD_INST_3(T) PSATD_INST_4(T) PSATD_INST_5(T) PSATD_INST_6(T)
 PSATD_INST_ALL(float)
 PSATD_INST_ALL(double)
 #endif

@@ -471,6 +471,38 @@ struct StepIO {
   int y_lo, y_hi, z_lo, z_hi;  // box lines needed after the inverse
 };
 
+// The compiled two-stage z kernel applies when a box's z tiles hold one column,
+// its z lines are transformed directly in exactly two stages, the pair of
+// radices is one of kZTwoStage and the tile fits the LDS of one workgroup.
+void two_stage_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
+  *ra = *rb = 0;
+  const LineSchedule& s = p->az.sch;
+  if (p->zcols != 1 || p->az.blue || s.nstages != 2) return;
+  for (const auto& pr : kZTwoStage)
+    if (pr[0] == s.radix[0] && pr[1] == s.radix[1] &&
+        (size_t)11 * two_stage_slots(pr[0], pr[1]) * csize <= lds_limit()) {
+      *ra = pr[0];
+      *rb = pr[1];
+      return;
+    }
+}
+
+// The compiled two-stage y kernels apply when the y lines are transformed
+// directly in exactly two stages whose radices are one of kYTwoStage, and a tile
+// of kYTwoStageLines lines fits in LDS with room for a second block per CU.
+void two_stage_y_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
+  *ra = *rb = 0;
+  const LineSchedule& s = p->ay.sch;
+  if (p->ay.blue || s.nstages != 2) return;
+  for (const auto& pr : kYTwoStage)
+    if (pr[0] == s.radix[0] && pr[1] == s.radix[1] &&
+        (size_t)kYTwoStageLines * two_stage_y_slots(pr[0], pr[1]) * csize <= lds_limit() / 2) {
+      *ra = pr[0];
+      *rb = pr[1];
+      return;
+    }
+}
+
 template <typename T>
 void set_ypass(YPassParams<T>& y, int nfields) {
   y.utiles = (y.u_hi - y.u_lo + y.nl - 1) / y.nl;
@@ -504,7 +536,7 @@ struct StepParams {
 
 // Kernel parameters of the five passes of one step of plan p with the given inputs / outputs.
 template <typename T>
-void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
+void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched = false) {
   const int NX = p->NX, NY = p->NY, NZ = p->NZ, NXH = p->NXH;
   const long long npts = p->npts;
   const uint32_t fbytes = (uint32_t)(npts * (long long)sizeof(cx<T>));
@@ -566,6 +598,8 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   y2.ps_out = NZ;
   y2.n = NY;
   y2.nl = p->nl_y;
+  if (!batched) two_stage_y_radices(p, sizeof(cx<T>), &y2.ra, &y2.rb);
+  if (y2.ra) y2.nl = kYTwoStageLines;
   y2.u_lo = 0;
   y2.u_hi = NZ;
   y2.nouter = NXH;
@@ -598,6 +632,7 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   z3.fd_NZ = make_fastdiv(NZ);
   z3.fd_ncol = make_fastdiv(p->zcols);
   z3.fft = line_fft<T>(p->az);
+  if (!batched) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
 
   YPassParams<T>& y4 = sp.y4;
   y4 = YPassParams<T>{};
@@ -615,6 +650,9 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp) {
   y4.ps_out = 1;
   y4.n = NY;
   y4.nl = p->nl_y;
+  y4.ra = y2.ra;
+  y4.rb = y2.rb;
+  if (y4.ra) y4.nl = kYTwoStageLines;
   y4.u_lo = io.z_lo;
   y4.u_hi = io.z_hi;
   y4.nouter = NXH;
@@ -1205,7 +1243,7 @@ int bind_batch(psatd_batch* b, void* const* g1) {
     psatd_plan* p = b->plans[i];
     const StepIO io = g1_io(p, g1, b->origins[i].data(), b->gd);
     StepParams<T> sp;
-    build_step<T>(p, io, sp);
+    build_step<T>(p, io, sp, true);
     x1[i] = sp.x1;
     y2[i] = sp.y2;
     z3[i] = sp.z3;
