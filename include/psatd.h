@@ -62,7 +62,14 @@ enum { PSATD_FP32 = 0, PSATD_FP64 = 1 };
 /* Plan descriptor.  Sizes are INTERIOR cells; the transformed box has
  * n + 2*ng cells per axis.  order: 0 = infinite order (exact k), otherwise an
  * even integer >= 2 used on all three axes.  dx, dy, dz > 0; dt != 0; c > 0;
- * eps0 > 0.  flags must be 0. */
+ * eps0 > 0.  flags: a combination of the PSATD_FLAG_* bits below. */
+enum {
+  /* The plan allocates no spectral workspace: it can only step through
+   * psatd_step_g1_noalloc (the other step calls and the autotuner return
+   * PSATD_ESTATE), and its box must fit that call's static scratch.  Not
+   * allowed for the boxes of a batch. */
+  PSATD_FLAG_NO_WORKSPACE = 2
+};
 typedef struct {
   int nx, ny, nz;
   int ngx, ngy, ngz;
@@ -119,6 +126,22 @@ int guard_merge(psatd_plan* plan, const void* const* box, void* const* g1, int n
  * group covering the whole periodic grid). */
 int psatd_step_g1(psatd_plan* plan, void* const* g1, const int origin[3], const int gdims[3],
                   void* stream);
+
+/* psatd_step_g1 without any allocation, for callers that cannot allocate
+ * device memory while stepping (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, same result, same
+ * kernels as psatd_step_g1; the two spectral workspaces live in a fixed
+ * device array of the library (256 MiB per GPU, held until the process ends)
+ * instead of the plan.  The box must fit it: 2 * 11 * (box_x/2+1) * box_y *
+ * box_z complex values of the plan's precision (e.g. 160^3 in FP32, 128^3 in
+ * FP64); larger boxes return PSATD_EINVAL.  The call itself does no hipMalloc,
+ * hipFree, event or stream creation.  All calls on one GPU share the array:
+ * calls that overlap on one GPU race, and a call on a stream other than the
+ * previous call's while that call still runs returns PSATD_ESTATE.  Nothing a
+ * call reads from the array was left there by an earlier call.  Plans made
+ * with PSATD_FLAG_NO_WORKSPACE hold only their tables. */
+int psatd_step_g1_noalloc(psatd_plan* plan, void* const* g1, const int origin[3], const int gdims[3],
+                          void* stream);
 
 /* Read-only plan properties (for bindings and benchmarks). */
 enum {

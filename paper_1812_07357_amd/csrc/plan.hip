@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -319,7 +320,7 @@ int validate(const psatd_plan_desc* d) {
   if (!(d->dt == d->dt) || d->dt == 0) return fail(PSATD_EINVAL, "dt must be non-zero");
   if (!(d->c > 0) || !(d->eps0 > 0)) return fail(PSATD_EINVAL, "c and eps0 must be > 0");
   if (d->precision != PSATD_FP32 && d->precision != PSATD_FP64) return fail(PSATD_EINVAL, "unknown precision");
-  if (d->flags != 0) return fail(PSATD_EINVAL, "flags must be 0");
+  if (d->flags & ~PSATD_FLAG_NO_WORKSPACE) return fail(PSATD_EINVAL, "unknown flags 0x%x", d->flags);
   const long long bx = (long long)d->nx + 2LL * d->ngx, by = (long long)d->ny + 2LL * d->ngy,
                   bz = (long long)d->nz + 2LL * d->ngz;
   if (bx > (1 << 20) || by > (1 << 20) || bz > (1 << 20)) return fail(PSATD_EINVAL, "box too large");
@@ -369,6 +370,55 @@ void choose_z_tile(psatd_plan* p, const LineSchedule& szs, int em, size_t cs) {
         p->zcols = c;
         break;
       }
+}
+
+// ---------------------------------------------------------------- static scratch
+// psatd_step_g1_noalloc runs the same five passes with their two spectral
+// workspaces in a fixed device array instead of the plan's own, so a step
+// allocates nothing (for callers that cannot allocate: graph capture, tight
+// serving loops).  Every GPU holds its own copy of the array for the life of
+// the process; its device address comes from hipGetSymbolAddress, once per
+// device, at plan creation (or the first call on a device).  The passes
+// overwrite every workspace element before reading it, so no call depends on
+// what an earlier call left there.  All calls on one GPU share the array:
+// calls that overlap in time on one GPU race (a call on a second stream while
+// the previous one is still running is refused with PSATD_ESTATE).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchSlot {
+  void* base = nullptr;  // device address of `scratch` on this device
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool known = false;
+};
+ScratchSlot g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Bytes of the two workspaces of plan p (each rounded up to 256 bytes).
+size_t scratch_half(const psatd_plan* p) { return ((size_t)p->npts * 11 * 2 * p->rsize + 255) & ~(size_t)255; }
+size_t scratch_need(const psatd_plan* p) { return 2 * scratch_half(p); }
+
+// The current device's slot, set up on first use: the array's address and the
+// event that marks the end of the last call.
+int scratch_slot(ScratchSlot** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return check_hip("hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(PSATD_EUNSUPPORTED, "device %d: static scratch slots exhausted", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  ScratchSlot& sl = g_scratch[dev];
+  if (!sl.base) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return check_hip("hipGetSymbolAddress");
+    if (!sl.done && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      sl.done = nullptr;
+      return check_hip("hipEventCreateWithFlags");
+    }
+    sl.base = ptr;
+  }
+  *out = &sl;
+  return PSATD_OK;
 }
 
 int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
@@ -429,8 +479,9 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   }
   if ((rc = dalloc(p, (void**)&p->kd, 8 * (size_t)(p->NXH + p->NY + p->NZ))) ||
       (rc = dalloc(p, &p->kw, p->rsize * (size_t)(p->NXH + p->NY + p->NZ))) ||
-      (rc = dalloc(p, &p->coef, 5 * p->rsize * npts)) || (rc = dalloc(p, &p->wsA, 11 * cs * npts)) ||
-      (rc = dalloc(p, &p->wsB, 11 * cs * npts))) {
+      (rc = dalloc(p, &p->coef, 5 * p->rsize * npts)) ||
+      (!(d->flags & PSATD_FLAG_NO_WORKSPACE) &&
+       ((rc = dalloc(p, &p->wsA, 11 * cs * npts)) || (rc = dalloc(p, &p->wsB, 11 * cs * npts))))) {
     std::string msg = g_err;
     free_plan(p);
     return fail(rc, "%s", msg.c_str());
@@ -451,6 +502,20 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
     if (!rc) rc = fail(PSATD_EHIP, "table build failed");
     free_plan(p);
     return rc;
+  }
+  if (d->flags & PSATD_FLAG_NO_WORKSPACE) {
+    // such a plan steps only through the static scratch: it must fit, and the
+    // scratch is located now so that the first step does no set-up
+    ScratchSlot* slot = nullptr;
+    if (scratch_need(p) > kScratchBytes)
+      rc = fail(PSATD_EINVAL, "box %dx%dx%d needs %zu bytes of workspace, above the %zu-byte static scratch", p->NX,
+                p->NY, p->NZ, scratch_need(p), kScratchBytes);
+    else
+      rc = scratch_slot(&slot);
+    if (rc) {
+      free_plan(p);
+      return rc;
+    }
   }
   *out = p;
   return PSATD_OK;
@@ -704,10 +769,10 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
 }
 
 template <typename T>
-int run_step(psatd_plan* p, const StepIO& io, hipStream_t s) {
+int run_step(psatd_plan* p, const StepIO& io, hipStream_t s, bool allow_timing = true) {
   Marks mk;
   mk.s = s;
-  if (p->timing) {
+  if (p->timing && allow_timing) {
     std::array<hipEvent_t, 6> set{};
     for (auto& e : set)
       if (hipEventCreate(&e) != hipSuccess) return check_hip("hipEventCreate");
@@ -1484,6 +1549,27 @@ int psatd_step_g1(psatd_plan* p, void* const* g1, const int origin[3], const int
   return dispatch_step(p, g1_io(p, g1, origin, gdims), (hipStream_t)stream);
 }
 
+int psatd_step_g1_noalloc(psatd_plan* p, void* const* g1, const int origin[3], const int gdims[3], void* stream) {
+  int rc = check_g1_call(p, g1, origin, gdims);
+  if (rc) return rc;
+  const size_t need = scratch_need(p);
+  if (need > kScratchBytes)
+    return fail(PSATD_EINVAL,
+                "psatd_step_g1_noalloc: the box needs %zu bytes of workspace, above the %zu-byte static scratch "
+                "(box %dx%dx%d)", need, kScratchBytes, p->NX, p->NY, p->NZ);
+  ScratchSlot* slot = nullptr;
+  if ((rc = scratch_slot(&slot))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const StreamGuard g{&slot->done, &slot->last_stream, &slot->known};
+  if ((rc = g.check(s, "psatd_step_g1_noalloc"))) return rc;
+  StepIO io = g1_io(p, g1, origin, gdims);
+  io.wsA = slot->base;
+  io.wsB = (char*)slot->base + scratch_half(p);
+  rc = p->fp64 ? run_step<double>(p, io, s, false) : run_step<float>(p, io, s, false);
+  if (rc) return rc;
+  return g.mark(s, "psatd_step_g1_noalloc");
+}
+
 int guard_fill(psatd_plan* p, const void* const* g1, void* const* box, int nfields, const int origin[3],
                const int gdims[3], void* stream) {
   if (!p || !g1 || !box) return fail(PSATD_EINVAL, "NULL argument");
@@ -1530,6 +1616,9 @@ int psatd_batch_create(int nsub, const psatd_plan_desc* subs, const int* origins
         a.eps0 != c.eps0)
       return fail(PSATD_EINVAL, "box %d: precision, cell size, dt, c and eps0 must agree across the batch", i);
   }
+  for (int i = 0; i < nsub; ++i)
+    if (subs[i].flags & PSATD_FLAG_NO_WORKSPACE)
+      return fail(PSATD_EINVAL, "box %d: batch boxes keep their own workspace (PSATD_FLAG_NO_WORKSPACE not allowed)", i);
   // Every box writes its interior back to G1 in the last pass of a step, while other
   // boxes of the same launch still run: two interiors sharing a G1 cell would race.
   for (int i = 0; i < nsub; ++i) {

@@ -23,6 +23,7 @@ PSATD_EUNSUPPORTED = -4
 PSATD_ESTATE = -5
 PSATD_FP32 = 0
 PSATD_FP64 = 1
+PSATD_FLAG_NO_WORKSPACE = 2
 
 Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS, Q_Z_COLUMNS = range(7)
 
@@ -73,6 +74,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.guard_merge.argtypes = [vp, vpp, vpp, cint, ip, ip, cint, vp]
     lib.psatd_step_g1.restype = cint
     lib.psatd_step_g1.argtypes = [vp, vpp, ip, ip, vp]
+    lib.psatd_step_g1_noalloc.restype = cint
+    lib.psatd_step_g1_noalloc.argtypes = [vp, vpp, ip, ip, vp]
     lib.psatd_plan_query.restype = cint
     lib.psatd_plan_query.argtypes = [vp, cint, ctypes.POINTER(ctypes.c_longlong)]
     lib.psatd_plan_tables.restype = cint
@@ -254,6 +257,14 @@ class Plan:
         self._check_fields(f, gshape, "step_g1")
         gdims = (gshape[2], gshape[1], gshape[0])
         _check(_lib.psatd_step_g1(self._h, _ptrs(f), _ints(origin), _ints(gdims), _stream(stream)))
+
+    def step_g1_noalloc(self, g1, origin, stream=None):
+        """psatd_step_g1_noalloc: the fused step with its workspace in the library's static scratch."""
+        f = self._split(g1, 11)
+        gshape = tuple(f[0].shape)
+        self._check_fields(f, gshape, "step_g1_noalloc")
+        gdims = (gshape[2], gshape[1], gshape[0])
+        _check(_lib.psatd_step_g1_noalloc(self._h, _ptrs(f), _ints(origin), _ints(gdims), _stream(stream)))
 
     def guard_fill(self, g1, box, origin, stream=None):
         """guard_fill: gather box arrays (interior + guards) from the periodic global arrays."""
