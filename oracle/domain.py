@@ -68,7 +68,7 @@ def local_step(g1, boxes, d, dt: float, c: float = 1.0, eps0: float = 1.0):
     """One step of the local (or hybrid, one box per group) solver on the global grid.
 
     g1: (11, NZ, NY, NX) fields of step n.  boxes: iterable of dicts with keys
-    origin, interior, nguard (scalar or triple) and order.  Every box is filled
+    origin, interior, nguard (scalar or triple), order and optionally staggered.  Every box is filled
     from step-n fields, pushed with its own order, and its interior E, B are
     written to a copy of g1, which is returned (sources unchanged).
     """
@@ -76,7 +76,7 @@ def local_step(g1, boxes, d, dt: float, c: float = 1.0, eps0: float = 1.0):
     out = g1.copy()
     for b in boxes:
         box = guard_fill(g1, b["origin"], b["interior"], b["nguard"])
-        eb = _step.box_step(box, d, dt, b["order"], c, eps0)
+        eb = _step.box_step(box, d, dt, b["order"], c, eps0, staggered=b.get("staggered", False))
         guard_merge(eb, out[0:6], b["origin"], b["interior"], b["nguard"])
     return out
 
@@ -89,9 +89,10 @@ def local_steps(g1, boxes, nsteps: int, d, dt: float, c: float = 1.0, eps0: floa
     return f
 
 
-def global_steps(g1, nsteps: int, d, dt: float, order, c: float = 1.0, eps0: float = 1.0):
+def global_steps(g1, nsteps: int, d, dt: float, order, c: float = 1.0, eps0: float = 1.0,
+                 staggered: bool = False):
     """The undecomposed periodic solve (no guards) for ``nsteps``; returns (11, ...)."""
     f = np.array(g1, dtype=np.float64, copy=True)
     for _ in range(nsteps):
-        f[0:6] = _step.box_step(f, d, dt, order, c, eps0)
+        f[0:6] = _step.box_step(f, d, dt, order, c, eps0, staggered=staggered)
     return f

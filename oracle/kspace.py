@@ -88,6 +88,87 @@ def modified_k_at(k, d: float, order: int):
     return kp
 
 
+# ------------------------------------------------------------------ staggered (Yee) grid
+# Reading for the staggered variant (the grid of the production PSATD codes the
+# paper builds on, Sec. 1.1 and 1.3): each component lives half a cell off the
+# nodes along the axes listed below, in slot order Ex Ey Ez Bx By Bz Jx Jy Jz
+# rho_old rho_new; array index i of a component stores its value at
+# (i + offset) d.  Derivatives are order-p staggered differences between
+# half-cell-shifted points.
+STAGGER_OFFSETS = ((1, 0, 0), (0, 1, 0), (0, 0, 1),
+                   (0, 1, 1), (1, 0, 1), (1, 1, 0),
+                   (1, 0, 0), (0, 1, 0), (0, 0, 1),
+                   (0, 0, 0), (0, 0, 0))
+
+
+def staggered_weights(order: int):
+    """Weights alpha_l (l = 1..p/2) of the order-p staggered first-derivative stencil.
+
+    f'(x) ~ sum_l alpha_l (f(x + (l - 1/2) d) - f(x - (l - 1/2) d)) / d, with the
+    closed form alpha_l = 1/(2l-1) prod_{j != l} (2j-1)^2 / ((2j-1)^2 - (2l-1)^2)
+    (derivative of the Lagrange interpolant on the nodes +-(2j-1)/2), in exact
+    rational arithmetic: 1 for p = 2; 9/8, -1/24 for p = 4.
+    """
+    if order <= 0 or order % 2:
+        raise ValueError("order must be a positive even integer")
+    m = order // 2
+    out = []
+    for l in range(1, m + 1):
+        a = Fraction(1, 2 * l - 1)
+        for j in range(1, m + 1):
+            if j != l:
+                a *= Fraction((2 * j - 1) ** 2, (2 * j - 1) ** 2 - (2 * l - 1) ** 2)
+        out.append(a)
+    return out
+
+
+def staggered_k_at(k, d: float, order: int):
+    """Symbol of the staggered difference at wavenumbers k: k for order 0, else
+    sum_l alpha_l 2 sin((2l - 1) k d / 2) / d."""
+    k = np.asarray(k, dtype=np.float64)
+    if order == 0:
+        return k.copy()
+    ks = np.zeros_like(k)
+    for l, a in enumerate(staggered_weights(order), start=1):
+        ks += float(a) * 2.0 * np.sin((2 * l - 1) * k * d / 2.0) / d
+    return ks
+
+
+def modified_k_staggered(n: int, d: float, order: int):
+    """Staggered modified wavenumber k_s of each DFT index along one axis.
+
+    The Nyquist index of an even axis is taken at k = +pi/d; unlike the centred
+    stencil, the staggered symbol does not vanish there (its value is the limit
+    of the two half-cell shift factors below, which keep real fields real).
+    """
+    ms, _ = signed_index(n)
+    k = 2.0 * np.pi * ms.astype(np.float64) / (n * d)
+    return staggered_k_at(k, d, order)
+
+
+def half_cell_shift(n: int, d: float):
+    """exp(i k d / 2) at the exact wavenumber of each DFT index (Nyquist at +pi/d, i.e. +i).
+
+    A component stored half a cell up (value at (i + 1/2) d under index i) has
+    grid-index spectrum exp(i k d / 2) times the spectrum of its values at the
+    true positions."""
+    ms, _ = signed_index(n)
+    k = 2.0 * np.pi * ms.astype(np.float64) / (n * d)
+    return np.exp(0.5j * k * d)
+
+
+def k_grids_staggered(shape, d, order):
+    """(Kx, Ky, Kz) staggered symbols and (Sx, Sy, Sz) half-cell shifts, broadcastable on (nz, ny, nx)."""
+    nz, ny, nx = shape
+    dx, dy, dz = (d, d, d) if np.isscalar(d) else d
+    px, py, pz = (order, order, order) if np.isscalar(order) else order
+    K = (modified_k_staggered(nx, dx, px)[None, None, :], modified_k_staggered(ny, dy, py)[None, :, None],
+         modified_k_staggered(nz, dz, pz)[:, None, None])
+    Sh = (half_cell_shift(nx, dx)[None, None, :], half_cell_shift(ny, dy)[None, :, None],
+          half_cell_shift(nz, dz)[:, None, None])
+    return K, Sh
+
+
 def k_grids(shape, d, order):
     """Broadcastable (Kx, Ky, Kz) for a box of shape (nz, ny, nx); ``d`` and ``order`` scalar or per axis (x, y, z)."""
     nz, ny, nx = shape

@@ -29,18 +29,24 @@ def mode_wavevectors(m, dims, d):
                      2 * np.pi * m[:, 2] / (dims[2] * dz)], axis=1)
 
 
-def push_modes(kvec, coef_in, d, dt: float, order, nsteps: int = 1, c: float = 1.0, eps0: float = 1.0):
+def push_modes(kvec, coef_in, d, dt: float, order, nsteps: int = 1, c: float = 1.0, eps0: float = 1.0,
+               staggered: bool = False):
     """Advance the complex mode amplitudes by ``nsteps`` PSATD steps, sources fixed.
 
     kvec: (nm, 3) physical wave vectors; coef_in: (11, nm) complex amplitudes of
     Ex Ey Ez Bx By Bz Jx Jy Jz rho_old rho_new.  ``order`` scalar or per axis.
     Returns (6, nm) complex amplitudes of E', B'.
+
+    ``staggered``: the amplitudes describe each component at its own staggered
+    position (``synthesize`` with the component's offset), where every
+    staggered difference acts on a mode as i times the real staggered symbol.
     """
     dx, dy, dz = (d, d, d) if np.isscalar(d) else d
     px, py, pz = (order, order, order) if np.isscalar(order) else order
-    K = (kspace.modified_k_at(kvec[:, 0], dx, px),
-         kspace.modified_k_at(kvec[:, 1], dy, py),
-         kspace.modified_k_at(kvec[:, 2], dz, pz))
+    sym = kspace.staggered_k_at if staggered else kspace.modified_k_at
+    K = (sym(kvec[:, 0], dx, px),
+         sym(kvec[:, 1], dy, py),
+         sym(kvec[:, 2], dz, pz))
     coef = kspace.coefficients(K[0], K[1], K[2], dt, c)
     a = np.array(coef_in, dtype=np.complex128, copy=True)
     for _ in range(nsteps):

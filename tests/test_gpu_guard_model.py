@@ -6,7 +6,10 @@ the plain local-vs-global comparison judges the pick and steps n_g up until
 it passes.  Against the plain method (scan n_g upwards, one comparison run per
 candidate) the result must be just as safe -- it passes the tolerance whenever
 the scan finds any passing n_g, and is never below the scan's smallest
-passing n_g -- while needing fewer comparison runs in total.
+passing n_g -- while needing fewer comparison runs in total.  Against the
+trivial rule that always takes the largest candidate (safe in one call), it
+must transform fewer cells: its boxes average under 0.9 of the largest
+candidate's, and it lands on the scan's optimum or the next width up.
 """
 
 import os
@@ -31,18 +34,27 @@ def test_network_choice_is_safe_and_needs_fewer_comparisons(lib):
     runs = [gm.Run(16, 0.5, 16.0, 0.1), gm.Run(64, 0.7, 24.0, 0.2), gm.Run(128, 0.4, 12.0, 0.15)]
     tol, steps = 1e-4, 32
     calls_model = calls_plain = 0
+    ratios, close = [], []
     for i, run in enumerate(runs):
         g1 = lvg.fields(run, synth.rng_for(600, i))
         r = gm.compare(model, lvg, run, g1, steps, tol)
-        print(run, r["pick"], r["model"], r["plain"], flush=True)
         g_plain = r["plain"]["nguard"]
         g_model = r["model"]["nguard"]
+        print(run, r["pick"], r["model"], r["plain"], r.get("cells_ratio_vs_largest"), flush=True)
         if g_plain is not None:
             assert g_model is not None and g_model >= g_plain
             assert r["model"]["log10_err"] <= np.log10(tol)
+            # the choice is the scan's optimum or the next candidate up
+            close.append(gm.GUARDS.index(g_model) - gm.GUARDS.index(g_plain) <= 1)
+            ratios.append(r["cells_ratio_vs_largest"])
         calls_model += r["model"]["judge_calls"]
         calls_plain += r["plain"]["judge_calls"]
     assert calls_model < calls_plain, (calls_model, calls_plain)
+    # Against the trivial rule "always take the largest guard" (one judge call, always safe,
+    # cells ratio 1): the network's boxes are smaller, i.e. it saves transformed cells.
+    print(f"judge calls {calls_model} vs {calls_plain}; box cells vs the largest guard: {ratios}", flush=True)
+    assert ratios and float(np.mean(ratios)) < 0.9, ratios
+    assert sum(close) >= len(close) - 1, close
     model.mlp.close()
 
 
