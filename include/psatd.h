@@ -64,6 +64,14 @@ enum { PSATD_FP32 = 0, PSATD_FP64 = 1 };
  * even integer >= 2 used on all three axes.  dx, dy, dz > 0; dt != 0; c > 0;
  * eps0 > 0.  flags: a combination of the PSATD_FLAG_* bits below. */
 enum {
+  /* Staggered (Yee) grid instead of the collocated one: Ex, Ey, Ez sit half a
+   * cell up along x, y, z; Bx, By, Bz half a cell up along (y, z), (x, z),
+   * (x, y); J like E; rho on the nodes.  Array index i of a component holds its
+   * value at (i + offset) d.  Derivatives are order-p staggered differences,
+   * sum_l a_l (f(x + (l - 1/2) d) - f(x - (l - 1/2) d)) / d (exact k at infinite
+   * order), the grid of the production PSATD codes the paper builds on (Sec.
+   * 1.1, 1.3).  The coefficient tables then hold the staggered symbol k_s. */
+  PSATD_FLAG_STAGGERED = 1,
   /* The plan allocates no spectral workspace: it can only step through
    * psatd_step_g1_noalloc (the other step calls and the autotuner return
    * PSATD_ESTATE), and its box must fit that call's static scratch.  Not
@@ -158,7 +166,7 @@ int psatd_plan_query(const psatd_plan* plan, int what, long long* value);
  * values, already multiplied by 1/(box_x*box_y*box_z), in the order
  * [kx][ky][kz] (kz fastest) with kx in [0, box_x/2] and ky, kz over all DFT
  * indices.  Followed by the three modified-wavenumber tables kx (box_x/2+1
- * values), ky (box_y), kz (box_z).  dst must hold
+ * values), ky (box_y), kz (box_z) (the staggered symbol k_s on staggered plans).  dst must hold
  * 5*PSATD_Q_SPECTRUM_POINTS + box_x/2+1 + box_y + box_z values. */
 int psatd_plan_tables(const psatd_plan* plan, void* dst, void* stream);
 

@@ -79,6 +79,13 @@ struct ZPushParams {
   const T* kx;           // NXH
   const T* ky;           // NY
   const T* kz;           // NZ
+  // Staggered grid (stag = 1): kappa = k_s exp(i k d / 2) per index, the symbol of
+  // a difference from the nodes to the half points above them (its conjugate for
+  // the way back); kx, ky, kz then hold k_s.
+  int stag;
+  const cx<T>* kxc;      // NXH
+  const cx<T>* kyc;      // NY
+  const cx<T>* kzc;      // NZ
   int NY, NZ, NXH;
   int ncol;              // (kx, ky) columns per tile
   int zgroup;            // lines per transform call (the lines of a tile are transformed in groups)
@@ -195,7 +202,9 @@ void launch_xinv(const XInvParams<T>& p, hipStream_t s);
 // Stage-major twiddle table of `sch` (see fft_lds.hpp), n entries allocated.
 void launch_twiddles(void* dst, const LineSchedule& sch, int fp64, hipStream_t s);
 void launch_bluestein(void* chirp, void* filt, int n, int m, int fp64, hipStream_t s);
-void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s);
+void launch_modk(double* dst, int n, int count, double d, int order, int staggered, hipStream_t s);
+// kappa = k_s exp(i k d / 2) of each DFT index at working precision (staggered grids).
+void launch_shifted(const double* ks, void* dst, int n, int count, int fp64, hipStream_t s);
 void launch_coef(void* coef, void* kxw, void* kyw, void* kzw, const double* kx, const double* ky,
                  const double* kz, int NXH, int NY, int NZ, double dt, double c, double norm, int fp64,
                  hipStream_t s);

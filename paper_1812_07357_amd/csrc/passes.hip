@@ -408,14 +408,62 @@ __device__ __forceinline__ void ypass_two_stage_body(const Src& S) {
 // tiles per CU overlap each other's loads and barriers instead.
 // The push at one k-space point: column col, z index kz, its field-0 value at LDS
 // slot s and field f at s + f * fs; k_x, k_y of the column given.
+// Staggered grid: the same update with the complex symbols kappa = k_s exp(i k d / 2)
+// (kp, from nodes to the half points above) and their conjugates (back down):
+//   E' = C E + i c^2 S1 (kappa^* x B) - (S1/eps0) J + i (c^2/eps0) kappa (X3 rho_old - X2 rho_new)
+//   B' = C B - i S1 (kappa x E) + i (X1/eps0) (kappa x J)
+// (E and J sit half a cell up along their own axis, B along the other two, rho on
+// the nodes; C, S1, X1..X3 are functions of |k_s|).
+template <typename T>
+__device__ __forceinline__ void push_point_staggered(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
+                                                     cx<T> kx, cx<T> ky, const T* cc) {
+  const T c2 = p.c2, ie = p.inv_eps0;
+  const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
+  const cx<T> kz_ = p.kzc[kz];
+  const cx<T> kxm = cconj(kx), kym = cconj(ky), kzm = cconj(kz_);
+  const cx<T> ex = lds[0 * fs + s], ey = lds[1 * fs + s], ez = lds[2 * fs + s];
+  const cx<T> bx = lds[3 * fs + s], by = lds[4 * fs + s], bz = lds[5 * fs + s];
+  const cx<T> jx = lds[6 * fs + s], jy = lds[7 * fs + s], jz = lds[8 * fs + s];
+  const cx<T> ro = lds[9 * fs + s], rn = lds[10 * fs + s];
+  // kappa^* x B, kappa x E, kappa x J
+  const cx<T> kbx = csub(cmul(kym, bz), cmul(kzm, by));
+  const cx<T> kby = csub(cmul(kzm, bx), cmul(kxm, bz));
+  const cx<T> kbz = csub(cmul(kxm, by), cmul(kym, bx));
+  const cx<T> kex = csub(cmul(ky, ez), cmul(kz_, ey));
+  const cx<T> key = csub(cmul(kz_, ex), cmul(kx, ez));
+  const cx<T> kez = csub(cmul(kx, ey), cmul(ky, ex));
+  const cx<T> kjx = csub(cmul(ky, jz), cmul(kz_, jy));
+  const cx<T> kjy = csub(cmul(kz_, jx), cmul(kx, jz));
+  const cx<T> kjz = csub(cmul(kx, jy), cmul(ky, jx));
+  const cx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
+  const T a = c2 * S1, g = c2 * ie, sj = S1 * ie, xj = X1 * ie;
+  const cx<T> ux = cadd(cscale(kbx, a), cscale(cmul(kx, rr), g));
+  const cx<T> uy = cadd(cscale(kby, a), cscale(cmul(ky, rr), g));
+  const cx<T> uz = cadd(cscale(kbz, a), cscale(cmul(kz_, rr), g));
+  lds[0 * fs + s] = {C * ex.re - sj * jx.re - ux.im, C * ex.im - sj * jx.im + ux.re};
+  lds[1 * fs + s] = {C * ey.re - sj * jy.re - uy.im, C * ey.im - sj * jy.im + uy.re};
+  lds[2 * fs + s] = {C * ez.re - sj * jz.re - uz.im, C * ez.im - sj * jz.im + uz.re};
+  const cx<T> wx = csub(cscale(kjx, xj), cscale(kex, S1));
+  const cx<T> wy = csub(cscale(kjy, xj), cscale(key, S1));
+  const cx<T> wz = csub(cscale(kjz, xj), cscale(kez, S1));
+  lds[3 * fs + s] = {C * bx.re - wx.im, C * bx.im + wx.re};
+  lds[4 * fs + s] = {C * by.re - wy.im, C * by.im + wy.re};
+  lds[5 * fs + s] = {C * bz.re - wz.im, C * bz.im + wz.re};
+}
+
 template <typename T>
 __device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int col, int kz,
-                                           T kx, T ky) {
+                                           int kxi, int kyi) {
   const T c2 = p.c2, ie = p.inv_eps0;
   const uint32_t idx = (uint32_t)(col * p.NZ + kz);
   T cc[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) cc[k] = gm<T>::ld(make_rsrc(p.coef + (i64)k * p.npts, p.coef_bytes), idx);
+  if (p.stag) {
+    push_point_staggered(p, lds, fs, s, kz, p.kxc[kxi], p.kyc[kyi], cc);
+    return;
+  }
+  const T kx = p.kx[kxi], ky = p.ky[kyi];
   const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
   const T kzz = p.kz[kz];
   const cx<T> ex = lds[0 * fs + s], ey = lds[1 * fs + s], ez = lds[2 * fs + s];
@@ -509,8 +557,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
         const int col = col0 + c;
         const int kxi = fdiv(col, p.fd_NY);
         const int kyi = col - kxi * p.NY;
-        const T kx = p.kx[kxi], ky = p.ky[kyi];
-        for (int kz = tid; kz < NZ; kz += nth) push_point(p, lds, fs, c * ld + lpad(kz), col, kz, kx, ky);
+        for (int kz = tid; kz < NZ; kz += nth) push_point(p, lds, fs, c * ld + lpad(kz), col, kz, kxi, kyi);
       }
     } else {
       // short lines: (column, k_z) pairs spread over the block
@@ -520,7 +567,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
         const int col = col0 + c;
         const int kxi = fdiv(col, p.fd_NY);
         const int kyi = col - kxi * p.NY;
-        push_point(p, lds, fs, c * ld + lpad(kz), col, kz, p.kx[kxi], p.ky[kyi]);
+        push_point(p, lds, fs, c * ld + lpad(kz), col, kz, kxi, kyi);
       }
     }
     __syncthreads();
@@ -629,8 +676,7 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
     {
       const int kxi = fdiv(col, p.fd_NY);
       const int kyi = col - kxi * p.NY;
-      const T kx = p.kx[kxi], ky = p.ky[kyi];
-      for (int kz = tid; kz < N; kz += NTH) push_point(p, lds, LD, kz, col, kz, kx, ky);
+      for (int kz = tid; kz < N; kz += NTH) push_point(p, lds, LD, kz, col, kz, kxi, kyi);
     }
     __syncthreads();
     // inverse stage A on the 6 lines of E and B, from LDS (natural order) back to rows

@@ -268,6 +268,7 @@ struct psatd_plan {
   int zcols = 0;     // (kx, ky) columns per P3 tile
   double* kd = nullptr;  // FP64 modified k: kx (NXH), ky (NY), kz (NZ)
   void* kw = nullptr;    // same at working precision
+  void* kwc = nullptr;   // staggered grids: kappa = k_s exp(i k d / 2) per axis index, complex
   void* coef = nullptr;  // 5 * npts
   void* wsA = nullptr;   // 11 * npts complex
   void* wsB = nullptr;   // 11 * npts complex
@@ -320,7 +321,8 @@ int validate(const psatd_plan_desc* d) {
   if (!(d->dt == d->dt) || d->dt == 0) return fail(PSATD_EINVAL, "dt must be non-zero");
   if (!(d->c > 0) || !(d->eps0 > 0)) return fail(PSATD_EINVAL, "c and eps0 must be > 0");
   if (d->precision != PSATD_FP32 && d->precision != PSATD_FP64) return fail(PSATD_EINVAL, "unknown precision");
-  if (d->flags & ~PSATD_FLAG_NO_WORKSPACE) return fail(PSATD_EINVAL, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(PSATD_FLAG_STAGGERED | PSATD_FLAG_NO_WORKSPACE))
+    return fail(PSATD_EINVAL, "unknown flags 0x%x", d->flags);
   const long long bx = (long long)d->nx + 2LL * d->ngx, by = (long long)d->ny + 2LL * d->ngy,
                   bz = (long long)d->nz + 2LL * d->ngz;
   if (bx > (1 << 20) || by > (1 << 20) || bz > (1 << 20)) return fail(PSATD_EINVAL, "box too large");
@@ -479,6 +481,7 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
   }
   if ((rc = dalloc(p, (void**)&p->kd, 8 * (size_t)(p->NXH + p->NY + p->NZ))) ||
       (rc = dalloc(p, &p->kw, p->rsize * (size_t)(p->NXH + p->NY + p->NZ))) ||
+      ((d->flags & PSATD_FLAG_STAGGERED) && (rc = dalloc(p, &p->kwc, 2 * p->rsize * (size_t)(p->NXH + p->NY + p->NZ)))) ||
       (rc = dalloc(p, &p->coef, 5 * p->rsize * npts)) ||
       (!(d->flags & PSATD_FLAG_NO_WORKSPACE) &&
        ((rc = dalloc(p, &p->wsA, 11 * cs * npts)) || (rc = dalloc(p, &p->wsB, 11 * cs * npts))))) {
@@ -491,9 +494,17 @@ int build_plan(const psatd_plan_desc* d, psatd_plan** out) {
     launch_twiddles(a->tw, a->sch, p->fp64, s);
     if (a->blue) launch_bluestein(a->chirp, a->filt, a->n, a->sch.n, p->fp64, s);
   }
-  launch_modk(p->kd, p->NX, p->NXH, d->dx, d->order, s);
-  launch_modk(p->kd + p->NXH, p->NY, p->NY, d->dy, d->order, s);
-  launch_modk(p->kd + p->NXH + p->NY, p->NZ, p->NZ, d->dz, d->order, s);
+  const int stag = (d->flags & PSATD_FLAG_STAGGERED) ? 1 : 0;
+  launch_modk(p->kd, p->NX, p->NXH, d->dx, d->order, stag, s);
+  launch_modk(p->kd + p->NXH, p->NY, p->NY, d->dy, d->order, stag, s);
+  launch_modk(p->kd + p->NXH + p->NY, p->NZ, p->NZ, d->dz, d->order, stag, s);
+  if (stag) {
+    char* kc = (char*)p->kwc;
+    const size_t cs1 = 2 * p->rsize;
+    launch_shifted(p->kd, kc, p->NX, p->NXH, p->fp64, s);
+    launch_shifted(p->kd + p->NXH, kc + cs1 * p->NXH, p->NY, p->NY, p->fp64, s);
+    launch_shifted(p->kd + p->NXH + p->NY, kc + cs1 * (p->NXH + p->NY), p->NZ, p->NZ, p->fp64, s);
+  }
   char* kw = (char*)p->kw;
   launch_coef(p->coef, kw, kw + p->rsize * p->NXH, kw + p->rsize * (p->NXH + p->NY), p->kd, p->kd + p->NXH,
               p->kd + p->NXH + p->NY, p->NXH, p->NY, p->NZ, d->dt, d->c, 1.0 / (double)p->ncell, p->fp64, s);
@@ -683,6 +694,13 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   z3.kx = kw;
   z3.ky = kw + NXH;
   z3.kz = kw + NXH + NY;
+  z3.stag = (p->d.flags & PSATD_FLAG_STAGGERED) ? 1 : 0;
+  if (z3.stag) {
+    const cx<T>* kc = (const cx<T>*)p->kwc;
+    z3.kxc = kc;
+    z3.kyc = kc + NXH;
+    z3.kzc = kc + NXH + NY;
+  }
   z3.NY = NY;
   z3.NZ = NZ;
   z3.NXH = NXH;

@@ -10,6 +10,7 @@
 //   The sine argument l k d = 2 pi l |m'| / n is reduced exactly in integers.
 //   k_p is odd in k and zero at the Nyquist index (it is zero there for every
 //   finite p, and kept zero at infinite order so that real fields stay real).
+//   The staggered (Yee) variant uses the staggered difference instead (below).
 // * PSATD coefficients per half-spectrum point, omega = c |K|, theta = omega dt:
 //       C = cos theta, S1 = sin theta / omega, X1 = (1 - C) / omega^2,
 //       X2 = (1 - S1/dt) / omega^2, X3 = (C - S1/dt) / omega^2,
@@ -98,10 +99,44 @@ __global__ void k_bluestein_filter(Tw<T>* dst, int n, int m) {
   put_tw(dst, k, re / m, im / m);
 }
 
-__global__ void k_modk(double* dst, int n, int count, double d, int order) {
+// Staggered variant (Yee grid): the symbol of the order-p staggered difference,
+//   k_s = sum_{l=1..m} a_l 2 sin((2l - 1) k d / 2) / d,
+//   a_l = 1/(2l-1) prod_{j != l} (2j-1)^2 / ((2j-1)^2 - (2l-1)^2),
+// or k itself at infinite order.  It does not vanish at the Nyquist index, which
+// is taken at k = +pi/d (together with the half-cell shifts below).
+__device__ double staggered_weight(int l, int m) {
+  double a = 1.0 / (double)(2 * l - 1);
+  const double ql = (double)(2 * l - 1) * (double)(2 * l - 1);
+  for (int j = 1; j <= m; ++j)
+    if (j != l) {
+      const double qj = (double)(2 * j - 1) * (double)(2 * j - 1);
+      a *= qj / (qj - ql);
+    }
+  return a;
+}
+
+__global__ void k_modk(double* dst, int n, int count, double d, int order, int staggered) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const long long ms = (2LL * i <= n) ? i : (long long)i - n;
+  if (staggered) {
+    const long long am = ms < 0 ? -ms : ms;
+    double ks;
+    if (order == 0) {
+      ks = 2.0 * (double)am / ((double)n * d) * 3.14159265358979323846;
+    } else {
+      const int m = order / 2;
+      double acc = 0.0;
+      for (int l = 1; l <= m; ++l) {
+        // sin((2l - 1) pi am / n), argument reduced modulo 2n exactly
+        const long long num = ((2LL * l - 1) * am) % (2LL * n);
+        acc += staggered_weight(l, m) * 2.0 * sinpi((double)num / (double)n);
+      }
+      ks = acc / d;
+    }
+    dst[i] = ms < 0 ? -ks : ks;
+    return;
+  }
   if (2LL * i == n) {  // Nyquist
     dst[i] = 0.0;
     return;
@@ -123,6 +158,19 @@ __global__ void k_modk(double* dst, int n, int count, double d, int order) {
     kp = acc / d;
   }
   dst[i] = ms < 0 ? -kp : kp;
+}
+
+// Staggered variant: kappa = k_s exp(i k d / 2) per DFT index (exact k; the
+// Nyquist index at +pi/d), the symbol of the difference from a node to the half
+// point above it; its conjugate goes from a half point down to the node.
+template <typename T>
+__global__ void k_shifted(const double* ks, cx<T>* dst, int n, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const long long ms = (2LL * i <= n) ? i : (long long)i - n;
+  double sn, cs;
+  sincospi((double)ms / (double)n, &sn, &cs);  // k d / 2 = pi ms / n
+  dst[i] = {T(ks[i] * cs), T(ks[i] * sn)};
 }
 
 template <typename T>
@@ -191,8 +239,15 @@ void launch_bluestein(void* chirp, void* filt, int n, int m, int fp64, hipStream
   }
 }
 
-void launch_modk(double* dst, int n, int count, double d, int order, hipStream_t s) {
-  hipLaunchKernelGGL(k_modk, dim3(nblk(count)), dim3(kT), 0, s, dst, n, count, d, order);
+void launch_modk(double* dst, int n, int count, double d, int order, int staggered, hipStream_t s) {
+  hipLaunchKernelGGL(k_modk, dim3(nblk(count)), dim3(kT), 0, s, dst, n, count, d, order, staggered);
+}
+
+void launch_shifted(const double* ks, void* dst, int n, int count, int fp64, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_shifted<double>, dim3(nblk(count)), dim3(kT), 0, s, ks, (cx<double>*)dst, n, count);
+  else
+    hipLaunchKernelGGL(k_shifted<float>, dim3(nblk(count)), dim3(kT), 0, s, ks, (cx<float>*)dst, n, count);
 }
 
 void launch_coef(void* coef, void* kxw, void* kyw, void* kzw, const double* kx, const double* ky,

@@ -23,6 +23,7 @@ PSATD_EUNSUPPORTED = -4
 PSATD_ESTATE = -5
 PSATD_FP32 = 0
 PSATD_FP64 = 1
+PSATD_FLAG_STAGGERED = 1
 PSATD_FLAG_NO_WORKSPACE = 2
 
 Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS, Q_Z_COLUMNS = range(7)
@@ -167,18 +168,20 @@ class Plan:
 
     Sizes are interior cells (x, y, z); ``nguard`` a scalar or per-axis
     triple; ``order`` 0 for infinite order, else even >= 2; ``dx`` scalar or
-    triple; ``precision`` "fp32" or "fp64".
+    triple; ``precision`` "fp32" or "fp64"; ``staggered`` for the staggered
+    (Yee) grid; ``flags`` further PSATD_FLAG_* bits.
     """
 
     def __init__(self, nx, ny, nz, nguard=0, order=0, dx=1.0, dt=0.5, c=1.0, eps0=1.0, precision="fp32",
-                 flags=0):
+                 flags=0, staggered=False):
         import torch
 
         g = _triple(nguard)
         d = _triple(dx)
+        flags = int(flags) | (PSATD_FLAG_STAGGERED if staggered else 0)
         desc = PlanDesc(int(nx), int(ny), int(nz), int(g[0]), int(g[1]), int(g[2]), int(order),
                         float(d[0]), float(d[1]), float(d[2]), float(dt), float(c), float(eps0),
-                        PSATD_FP64 if precision == "fp64" else PSATD_FP32, int(flags))
+                        PSATD_FP64 if precision == "fp64" else PSATD_FP32, flags)
         h = ctypes.c_void_p()
         _check(_lib.psatd_plan_create_ex(ctypes.byref(desc), ctypes.byref(h)))
         self._h = h
@@ -190,6 +193,7 @@ class Plan:
         self.c = float(c)
         self.eps0 = float(eps0)
         self.precision = "fp64" if precision == "fp64" else "fp32"
+        self.staggered = bool(flags & PSATD_FLAG_STAGGERED)
         self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
         self.box = (self.query(Q_BOX_X), self.query(Q_BOX_Y), self.query(Q_BOX_Z))
 
@@ -339,7 +343,8 @@ class Batch:
     """Many boxes of one periodic global grid, advanced together (psatd_batch_*).
 
     ``boxes``: iterable of dicts with ``origin`` (x, y, z), ``interior``
-    (nx, ny, nz), ``nguard`` (scalar or triple) and ``order``; ``gdims`` =
+    (nx, ny, nz), ``nguard`` (scalar or triple), ``order`` and optionally
+    ``staggered`` (Yee grid, PSATD_FLAG_STAGGERED); ``gdims`` =
     (GX, GY, GZ).  Each pass of a step is one persistent launch over all boxes;
     ``run`` replays ``nsteps`` steps from a captured hipGraph.
     """
@@ -356,7 +361,8 @@ class Batch:
             n = b["interior"]
             descs[i] = PlanDesc(int(n[0]), int(n[1]), int(n[2]), int(g[0]), int(g[1]), int(g[2]), int(b["order"]),
                                 float(d[0]), float(d[1]), float(d[2]), float(dt), float(c), float(eps0),
-                                PSATD_FP64 if precision == "fp64" else PSATD_FP32, 0)
+                                PSATD_FP64 if precision == "fp64" else PSATD_FP32,
+                                PSATD_FLAG_STAGGERED if b.get("staggered", False) else 0)
             for a in range(3):
                 origins[3 * i + a] = int(b["origin"][a])
         h = ctypes.c_void_p()

@@ -48,7 +48,7 @@ def _desc(lib, **kw):
 
 @pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-3), dict(ngz=-1), dict(order=3), dict(order=-2),
                                  dict(dx=0.0), dict(dt=0.0), dict(c=-1.0), dict(eps0=0.0), dict(precision=7),
-                                 dict(flags=1), dict(dt=float("nan"))])
+                                 dict(flags=4), dict(flags=-1), dict(dt=float("nan"))])
 def test_invalid_descriptors_are_rejected_on_the_host(lib, bad):
     h = ctypes.c_void_p()
     rc = lib._lib.psatd_plan_create_ex(ctypes.byref(_desc(lib, **bad)), ctypes.byref(h))
