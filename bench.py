@@ -122,14 +122,15 @@ def traffic_from_profile(kernel_pass, digest):
     return None if entry is None else entry.get("bytes_per_launch")
 
 
-def run_gpu(precision, inputs_host, steps, warmup):
+def run_gpu(precision, inputs_host, steps, warmup, staggered=False):
     import torch
 
     from paper_1812_07357_amd import psatd
 
     nx, ny, nz = INTERIOR
     dtype = torch.float64 if precision == "fp64" else torch.float32
-    plan = psatd.Plan(nx, ny, nz, nguard=NGUARD, order=ORDER, dx=DX, dt=DT, precision=precision)
+    plan = psatd.Plan(nx, ny, nz, nguard=NGUARD, order=ORDER, dx=DX, dt=DT, precision=precision,
+                      staggered=staggered)
     plan.autotune()
     schedule = {"xyz"[a]: plan.schedule(a) for a in range(3)}
     g1 = torch.as_tensor(inputs_host, dtype=dtype).to("cuda")
@@ -360,6 +361,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-staggered", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--extra", action="store_true",
@@ -465,6 +467,14 @@ def main():
         }
         del f64, e
     del f32
+
+    if not args.no_staggered:
+        log("fp32 staggered-grid run")
+        rs, fs = run_gpu("fp32", host, args.steps, args.warmup, staggered=True)
+        del fs
+        out["staggered_fp32"] = {"value": interior_cells / (rs["ms_per_step"] * 1e-3), "ms_per_step": rs["ms_per_step"],
+                                 "passes_ms": {k: round(v, 4) for k, v in rs["passes_ms"].items()},
+                                 "note": "same workload on the staggered (Yee) grid, PSATD_FLAG_STAGGERED"}
 
     if not args.no_batch:
         log("batch run (64 uneven boxes, hipGraph)")
