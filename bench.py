@@ -133,6 +133,7 @@ def run_gpu(precision, inputs_host, steps, warmup, staggered=False):
                       staggered=staggered)
     plan.autotune()
     schedule = {"xyz"[a]: plan.schedule(a) for a in range(3)}
+    schedule["two_stage_passes"] = [PASSES[i] for i in range(5) if (plan.query(psatd.Q_TWO_STAGE) >> i) & 1]
     g1 = torch.as_tensor(inputs_host, dtype=dtype).to("cuda")
     origin = (0, 0, 0)
     for _ in range(warmup):

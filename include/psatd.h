@@ -157,7 +157,10 @@ enum {
   PSATD_Q_PRECISION = 3,
   PSATD_Q_WORKSPACE_BYTES = 4,  /* device bytes owned by the plan */
   PSATD_Q_SPECTRUM_POINTS = 5,  /* (box_x/2+1) * box_y * box_z */
-  PSATD_Q_Z_COLUMNS = 6         /* (kx, ky) columns per tile of the k-space pass */
+  PSATD_Q_Z_COLUMNS = 6,        /* (kx, ky) columns per tile of the k-space pass */
+  PSATD_Q_TWO_STAGE = 7         /* bit i set: pass i+1 of the step runs a kernel compiled for its
+                                   two-stage line schedule (x forward, y forward, k-space, y inverse,
+                                   x inverse); the autotuner keeps the faster kernel per pass */
 };
 int psatd_plan_query(const psatd_plan* plan, int what, long long* value);
 

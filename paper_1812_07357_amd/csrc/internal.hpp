@@ -43,6 +43,7 @@ struct XFwdParams {
   FastDiv fd_ytiles, fd_NZ, fd_NX, fd_GX, fd_GY, fd_GZ, fd_nc;
   int ld_drow, ld_dcol;  // block stride over (complex line, x) = divmod(threads, NX)
   int wr_drow, wr_dcol;  // block stride over (kx, complex line) = divmod(threads, ty / 2)
+  int ra, rb;            // two-stage kernel with compile-time radices (ty = 2 kXTwoStageLines), or 0, 0
   LineFFT<T> fft;
 };
 
@@ -120,6 +121,7 @@ struct XInvParams {
   FastDiv fd_ytiles, fd_nz, fd_nc, fd_NX, fd_GX, fd_GY, fd_GZ;
   int nthreads;          // block size the tile was fitted for (kXInvThreads, or kLineThreads
                          // when a line's butterflies exceed the smaller block)
+  int ra, rb;            // two-stage kernel with compile-time radices (ty = 2 kXTwoStageLines), or 0, 0
   LineFFT<T> fft;
 };
 
@@ -139,6 +141,14 @@ constexpr int kYTwoStageLines = 16;
 constexpr int two_stage_y_slots(int ra, int rb) { return (rb * (ra | 1)) | 1; }
 constexpr int two_stage_y_threads(int ra, int rb) {
   return ((kYTwoStageLines * (ra > rb ? ra : rb) + 63) / 64) * 64;
+}
+
+// Line schedules (RA, RB) with compiled two-stage x kernels (single boxes), complex
+// lines (pairs of real rows) per tile, and block size (one butterfly per thread).
+constexpr int kXTwoStage[][2] = {{24, 24}, {32, 18}, {18, 32}, {16, 20}, {20, 16}, {16, 16}, {32, 17}, {17, 32}};
+constexpr int kXTwoStageLines = 8;
+constexpr int two_stage_x_threads(int ra, int rb) {
+  return ((kXTwoStageLines * (ra > rb ? ra : rb) + 63) / 64) * 64;
 }
 
 // Threads per block of the x and y passes.

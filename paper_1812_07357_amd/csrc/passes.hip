@@ -186,6 +186,254 @@ __device__ __forceinline__ void xfwd_body(const Src& S) {
   }
 }
 
+// ------------------------------------------------------------------ P1 / P5, two-stage lines
+// The x passes of a single box for lines of N = RA * RB points with compile-time
+// radices (the stage structure of the two-stage y and z kernels), NL complex
+// lines (2 NL real rows) per tile.  P1: stage A gathers each butterfly's RA
+// points of its two real rows straight from G1 (or the box) into registers,
+// stage B leaves the transform in natural order in LDS, and the split into the
+// two rows' half spectra is written as before.  P5: the half spectra of two
+// rows are rebuilt into a full line in LDS, both stages run from LDS, and the
+// rows (real part to one, imaginary part to the other) are written along x from
+// the natural-order line: stage B's own outputs are RA points apart, and
+// storing them straight from registers would split every wave's stores into
+// short runs of several rows.
+template <typename T, int RA, int RB, int NL, int NTH>
+__device__ __forceinline__ void xfwd_two_stage_body(const XFwdParams<T>& p) {
+  constexpr int N = RA * RB, PA = RA | 1, LD = two_stage_slots(RA, RB);
+  cx<T>* lds = lds_base<T>();
+  int* xoff = reinterpret_cast<int*>(lds + NL * LD);  // source column of each box x (G1 wrap applied)
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NTH) xoff[i] = p.gather ? fmod_i(p.x0 + i, p.fd_GX) : i;
+  __syncthreads();
+  const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);
+  const int NY = p.NY, NXH = p.NXH;
+  const int rowlen = p.gather ? p.GX : N;
+  for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+    const int q = fdiv(tile, p.fd_ytiles);
+    const int ybase = (tile - q * p.ytiles) * (2 * NL);
+    const int f = fdiv(q, p.fd_NZ);
+    const int z = q - f * p.NZ;
+    const int zrow = p.gather ? fmod_i(p.z0 + z, p.fd_GZ) * p.GY : z * NY;
+    // stage A: rows a = ybase + 2c, b = a + 1 of line c as one complex line
+    {
+      const rsrc_t src = make_rsrc(p.src[f], p.src_bytes);
+#pragma unroll
+      for (int b0 = 0; b0 < NL * RB; b0 += NTH) {
+        const int bi = b0 + tid;
+        if (b0 + NTH <= NL * RB || bi < NL * RB) {
+          const int c = bi / RB, j = bi - c * RB;
+          const int ya = ybase + 2 * c;
+          int ra = ya, rb = ya + 1;
+          if (p.gather) {
+            ra = fmod_i(p.y0 + ya, p.fd_GY);
+            rb = fmod_i(p.y0 + ya + 1, p.fd_GY);
+          }
+          const uint32_t oa = ya < NY ? (uint32_t)((zrow + ra) * rowlen) : kOOB;
+          const uint32_t ob = ya + 1 < NY ? (uint32_t)((zrow + rb) * rowlen) : kOOB;
+          cx<T> v[RA];
+#pragma unroll
+          for (int t = 0; t < RA; ++t) {
+            const int xs = xoff[j + RB * t];
+            v[t] = {gm<T>::ld(src, oa + (uint32_t)xs), gm<T>::ld(src, ob + (uint32_t)xs)};
+          }
+          dft<RA, -1, T>::run(v);
+          cx<T>* y = lds + c * LD + j * PA;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) y[t] = v[t];
+        }
+      }
+    }
+    __syncthreads();
+    // stage B: rows -> twiddles -> DFT -> natural order (in place, after all reads)
+    {
+      constexpr int NBR = (NL * RA + NTH - 1) / NTH;
+      cx<T> v[NBR][RB];
+#pragma unroll
+      for (int u = 0; u < NBR; ++u) {
+        const int bi = u * NTH + tid;
+        if (bi < NL * RA) {
+          const int c = bi / RA, k = bi - c * RA;
+          const cx<T>* y = lds + c * LD + k;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) v[u][t] = y[t * PA];
+          const Tw<T>* w = twb + k * (RB - 1) - 1;
+          if (k > 0) {
+#pragma unroll
+            for (int t = 1; t < RB; ++t) v[u][t] = twmul<-1>(v[u][t], w[t]);
+          }
+          dft<RB, -1, T>::run(v[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NBR; ++u) {
+        const int bi = u * NTH + tid;
+        if (bi < NL * RA) {
+          const int c = bi / RA, k = bi - c * RA;
+          cx<T>* zl = lds + c * LD + k;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) zl[t * RA] = v[u][t];
+        }
+      }
+    }
+    __syncthreads();
+    // split each complex line into the half spectra of its two real rows, written as pairs
+    const rsrc_t dst = make_rsrc(p.dst + (i64)f * p.npts, p.dst_bytes);
+    const int ny_t = min(2 * NL, NY - ybase);
+    for (int e = tid; e < NXH * NL; e += NTH) {
+      const int kx = e / NL, c = e - kx * NL;
+      const cx<T> za = lds[c * LD + kx];
+      const cx<T> zb = cconj(lds[c * LD + (kx == 0 ? 0 : N - kx)]);
+      const cx<T> sum = cadd(za, zb), dif = csub(za, zb);
+      const cx<T> va = cscale(sum, T(0.5));
+      const cx<T> vb = {T(0.5) * dif.im, T(-0.5) * dif.re};
+      const int t = 2 * c;
+      const uint32_t o = (uint32_t)((z * NXH + kx) * NY + ybase + t);
+      if (t + 1 < ny_t)
+        gm<T>::stc2(dst, o, va, vb);
+      else if (t < ny_t)
+        gm<T>::stc(dst, o, va);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int RA, int RB, int NL, int NTH>
+__device__ __forceinline__ void xinv_two_stage_body(const XInvParams<T>& p) {
+  constexpr int N = RA * RB, PA = RA | 1, LD = two_stage_slots(RA, RB);
+  cx<T>* lds = lds_base<T>();
+  const int tid = threadIdx.x;
+  const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);
+  const int NY = p.NY, NXH = p.NXH;
+  for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+    const int q = fdiv(tile, p.fd_ytiles);
+    const int ybase = p.y_lo + (tile - q * p.ytiles) * (2 * NL);
+    const int f = fdiv(q, p.fd_nz);
+    const int z = p.z_lo + (q - f * (p.z_hi - p.z_lo));
+    // rebuild Z = A + i B over the full line from the half spectra of rows 2c, 2c + 1;
+    // every load of the tile is issued before the first LDS write
+    {
+      constexpr int NH = N / 2 + 1;
+      constexpr int NR = (NH * NL + NTH - 1) / NTH;
+      const rsrc_t src = make_rsrc(p.src + (i64)f * p.npts, p.src_bytes);
+      const int sbase = z * NXH * NY;
+      cx<T> xa[NR], xb[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int e = r * NTH + tid;
+        const int kx = e / NL, c = e - kx * NL;
+        const int ya = ybase + 2 * c;
+        const bool ok = e < NH * NL;
+        xa[r] = gm<T>::ldc(src, ok && ya < p.y_hi ? (uint32_t)(sbase + kx * NY + ya) : kOOB);
+        xb[r] = gm<T>::ldc(src, ok && ya + 1 < p.y_hi ? (uint32_t)(sbase + kx * NY + ya + 1) : kOOB);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int e = r * NTH + tid;
+        if (e >= NH * NL) break;
+        const int kx = e / NL, c = e - kx * NL;
+        cx<T> x = xa[r], y = xb[r];
+        const bool selfconj = (kx == 0) || (2 * kx == N);
+        if (selfconj) {
+          x.im = T(0);
+          y.im = T(0);
+        }
+        lds[c * LD + kx] = {x.re - y.im, x.im + y.re};
+        if (!selfconj) lds[c * LD + (N - kx)] = {x.re + y.im, y.re - x.im};
+      }
+    }
+    __syncthreads();
+    // stage A from the natural-order line, in place after all reads
+    {
+      constexpr int NAR = (NL * RB + NTH - 1) / NTH;
+      cx<T> v[NAR][RA];
+#pragma unroll
+      for (int u = 0; u < NAR; ++u) {
+        const int bi = u * NTH + tid;
+        if (bi < NL * RB) {
+          const int c = bi / RB, j = bi - c * RB;
+          const cx<T>* x = lds + c * LD + j;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) v[u][t] = x[RB * t];
+          dft<RA, 1, T>::run(v[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NAR; ++u) {
+        const int bi = u * NTH + tid;
+        if (bi < NL * RB) {
+          const int c = bi / RB, j = bi - c * RB;
+          cx<T>* y = lds + c * LD + j * PA;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) y[t] = v[u][t];
+        }
+      }
+    }
+    __syncthreads();
+    // stage B: rows -> twiddles -> DFT -> natural order (in place, after all reads)
+    {
+      constexpr int NBR = (NL * RA + NTH - 1) / NTH;
+      cx<T> v[NBR][RB];
+#pragma unroll
+      for (int u = 0; u < NBR; ++u) {
+        const int bi = u * NTH + tid;
+        if (bi < NL * RA) {
+          const int c = bi / RA, k = bi - c * RA;
+          const cx<T>* y = lds + c * LD + k;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) v[u][t] = y[t * PA];
+          const Tw<T>* w = twb + k * (RB - 1) - 1;
+          if (k > 0) {
+#pragma unroll
+            for (int t = 1; t < RB; ++t) v[u][t] = twmul<1>(v[u][t], w[t]);
+          }
+          dft<RB, 1, T>::run(v[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NBR; ++u) {
+        const int bi = u * NTH + tid;
+        if (bi < NL * RA) {
+          const int c = bi / RA, k = bi - c * RA;
+          cx<T>* zl = lds + c * LD + k;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) zl[t * RA] = v[u][t];
+        }
+      }
+    }
+    __syncthreads();
+    // the two real rows of each line (box, or interior of G1), written along x so that
+    // a wave's stores cover whole rows
+    {
+      const rsrc_t dst = make_rsrc(p.dst[f], p.dst_bytes);
+      const int zrow = p.scatter ? fmod_i(p.oz + z - p.gz, p.fd_GZ) * p.GY : z * NY;
+      const int rowlen = p.scatter ? p.GX : N;
+      for (int e = tid; e < NL * N; e += NTH) {
+        const int c = e / N, n = e - c * N;
+        const cx<T> val = lds[c * LD + n];
+        const int ya = ybase + 2 * c;
+        uint32_t ia = kOOB, ib = kOOB;
+        if (!p.scatter) {
+          if (ya < p.y_hi) ia = (uint32_t)((zrow + ya) * rowlen + n);
+          if (ya + 1 < p.y_hi) ib = (uint32_t)((zrow + ya + 1) * rowlen + n);
+        } else if (n >= p.gx && n < p.gx + p.nx) {
+          // the interior is no larger than the grid and its origin lies in it: one wrap at most
+          const int xg = wrap_once(p.ox + n - p.gx, p.GX);
+          const int ra = wrap_once(p.oy + ya - p.gy, p.GY);
+          if (ya < p.y_hi) ia = (uint32_t)((zrow + ra) * rowlen + xg);
+          if (ya + 1 < p.y_hi) ib = (uint32_t)((zrow + wrap_once(ra + 1, p.GY)) * rowlen + xg);
+        }
+        gm<T>::st(dst, ia, val.re);
+        gm<T>::st(dst, ib, val.im);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ P2 / P4
 // Tiles are y-lines (about 5k elements); loads go to LDS in rounds of
 // load_round values per thread, and several blocks per CU overlap each other.
@@ -874,6 +1122,20 @@ k_zpush_b(BatchArgs<ZPushParams<T>> a) {
 }
 // x inverse: at most 128 registers in FP32; 256-thread blocks (four per CU) unless
 // the lines need the larger block.
+template <typename T, int RA, int RB>
+__global__ void __launch_bounds__(two_stage_x_threads(RA, RB))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_xfwd2(XFwdParams<T>) {
+  xfwd_two_stage_body<T, RA, RB, kXTwoStageLines, two_stage_x_threads(RA, RB)>(
+      *(const XFwdParams<T>*)__builtin_amdgcn_kernarg_segment_ptr());
+}
+// x inverse, two-stage: 168 registers in FP32 (its stage A holds a butterfly across a
+// barrier); the LDS of a tile already limits a CU to four blocks of three waves.
+template <typename T, int RA, int RB>
+__global__ void __launch_bounds__(two_stage_x_threads(RA, RB))
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) k_xinv2(XInvParams<T>) {
+  xinv_two_stage_body<T, RA, RB, kXTwoStageLines, two_stage_x_threads(RA, RB)>(
+      *(const XInvParams<T>*)__builtin_amdgcn_kernarg_segment_ptr());
+}
 template <int S, typename T, int RA, int RB>
 __global__ void __launch_bounds__(two_stage_y_threads(RA, RB))
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) k_ypass2(YPassParams<T>) {
@@ -951,8 +1213,36 @@ size_t xinv_lds(const XInvParams<T>& p) {
   return (size_t)(p.ty / 2) * fft_slots(p.fft.sch.n) * cx_bytes<T>();
 }
 
+template <typename T, int I = 0>
+void launch_xfwd_two_stage_at(const XFwdParams<T>& p, hipStream_t s) {
+  if constexpr (I < (int)(sizeof(kXTwoStage) / sizeof(kXTwoStage[0]))) {
+    constexpr int RA = kXTwoStage[I][0], RB = kXTwoStage[I][1];
+    if (p.ra == RA && p.rb == RB) {
+      const size_t lds = (size_t)kXTwoStageLines * two_stage_slots(RA, RB) * cx_bytes<T>() + (size_t)RA * RB * sizeof(int);
+      launch_persistent(k_xfwd2<T, RA, RB>, p, two_stage_x_threads(RA, RB), lds, p.ntiles, s);
+      return;
+    }
+    launch_xfwd_two_stage_at<T, I + 1>(p, s);
+  }
+}
+template <typename T, int I = 0>
+void launch_xinv_two_stage_at(const XInvParams<T>& p, hipStream_t s) {
+  if constexpr (I < (int)(sizeof(kXTwoStage) / sizeof(kXTwoStage[0]))) {
+    constexpr int RA = kXTwoStage[I][0], RB = kXTwoStage[I][1];
+    if (p.ra == RA && p.rb == RB) {
+      const size_t lds = (size_t)kXTwoStageLines * two_stage_slots(RA, RB) * cx_bytes<T>();
+      launch_persistent(k_xinv2<T, RA, RB>, p, two_stage_x_threads(RA, RB), lds, p.ntiles, s);
+      return;
+    }
+    launch_xinv_two_stage_at<T, I + 1>(p, s);
+  }
+}
 template <typename T>
 void launch_xfwd(const XFwdParams<T>& p, hipStream_t s) {
+  if (p.ra > 0) {
+    launch_xfwd_two_stage_at<T>(p, s);
+    return;
+  }
   launch_persistent(k_xfwd<T>, p, kLineThreads, xfwd_lds(p), p.ntiles, s);
 }
 template <typename T, int I = 0>
@@ -1023,6 +1313,10 @@ void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
 }
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
+  if (p.ra > 0) {
+    launch_xinv_two_stage_at<T>(p, s);
+    return;
+  }
   if (p.nthreads == kXInvThreads)
     launch_persistent(k_xinv<T, kXInvThreads>, p, kXInvThreads, xinv_lds(p), p.ntiles, s);
   else

@@ -252,6 +252,11 @@ size_t csz() {
 
 }  // namespace
 
+namespace {
+// Default set of passes on two-stage kernels (bit i = P(i+1)): all but the x inverse.
+constexpr int kTwoStageDefault = 1 | 2 | 4 | 8;
+}  // namespace
+
 struct psatd_plan {
   psatd_plan_desc d{};
   int NX = 0, NY = 0, NZ = 0, NXH = 0;
@@ -266,6 +271,10 @@ struct psatd_plan {
   int nl_y = 0;      // lines per P2/P4 tile
   int zthreads = 0;  // threads of the P3 block
   int zcols = 0;     // (kx, ky) columns per P3 tile
+  // Passes (bit i = P(i+1)) that run the compiled two-stage kernel when their
+  // schedule has one; the autotuner keeps a pass's bit only if that kernel is the
+  // faster of the two.  The x inverse starts on the run-time-schedule kernel.
+  int two_stage_mask = kTwoStageDefault;
   double* kd = nullptr;  // FP64 modified k: kx (NXH), ky (NY), kz (NZ)
   void* kw = nullptr;    // same at working precision
   void* kwc = nullptr;   // staggered grids: kappa = k_s exp(i k d / 2) per axis index, complex
@@ -563,6 +572,23 @@ void two_stage_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
     }
 }
 
+// The compiled two-stage x kernels apply to single boxes whose x lines are transformed
+// directly in exactly two stages with radices in kXTwoStage, the tile (and P1's
+// column table) fitting in a quarter of the LDS a workgroup may use.
+void two_stage_x_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
+  *ra = *rb = 0;
+  const LineSchedule& s = p->ax.sch;
+  if (p->ax.blue || s.nstages != 2) return;
+  for (const auto& pr : kXTwoStage)
+    if (pr[0] == s.radix[0] && pr[1] == s.radix[1] &&
+        (size_t)kXTwoStageLines * two_stage_slots(pr[0], pr[1]) * csize + (size_t)p->NX * sizeof(int) <=
+            lds_limit() / 3) {
+      *ra = pr[0];
+      *rb = pr[1];
+      return;
+    }
+}
+
 // The compiled two-stage y kernels apply when the y lines are transformed
 // directly in exactly two stages whose radices are one of kYTwoStage, and a tile
 // of kYTwoStageLines lines fits in LDS with room for a second block per CU.
@@ -657,6 +683,19 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   x1.wr_drow = nth / (x1.ty / 2);
   x1.wr_dcol = nth % (x1.ty / 2);
   x1.fft = line_fft<T>(p->ax);
+  int xra = 0, xrb = 0;
+  if (!batched) two_stage_x_radices(p, sizeof(cx<T>), &xra, &xrb);
+  if (p->two_stage_mask & 1) {
+    x1.ra = xra;
+    x1.rb = xrb;
+  }
+  if (x1.ra) {  // tiles of kXTwoStageLines complex lines
+    x1.ty = 2 * kXTwoStageLines;
+    x1.ytiles = (NY + x1.ty - 1) / x1.ty;
+    x1.ntiles = 11 * NZ * x1.ytiles;
+    x1.fd_ytiles = make_fastdiv(x1.ytiles);
+    x1.fd_nc = make_fastdiv(x1.ty / 2);
+  }
 
   YPassParams<T>& y2 = sp.y2;
   y2 = YPassParams<T>{};
@@ -674,7 +713,12 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   y2.ps_out = NZ;
   y2.n = NY;
   y2.nl = p->nl_y;
-  if (!batched) two_stage_y_radices(p, sizeof(cx<T>), &y2.ra, &y2.rb);
+  int yra = 0, yrb = 0;
+  if (!batched) two_stage_y_radices(p, sizeof(cx<T>), &yra, &yrb);
+  if (p->two_stage_mask & 2) {
+    y2.ra = yra;
+    y2.rb = yrb;
+  }
   if (y2.ra) y2.nl = kYTwoStageLines;
   y2.u_lo = 0;
   y2.u_hi = NZ;
@@ -715,7 +759,7 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   z3.fd_NZ = make_fastdiv(NZ);
   z3.fd_ncol = make_fastdiv(p->zcols);
   z3.fft = line_fft<T>(p->az);
-  if (!batched) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
+  if (!batched && (p->two_stage_mask & 4)) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
 
   YPassParams<T>& y4 = sp.y4;
   y4 = YPassParams<T>{};
@@ -733,8 +777,10 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   y4.ps_out = 1;
   y4.n = NY;
   y4.nl = p->nl_y;
-  y4.ra = y2.ra;
-  y4.rb = y2.rb;
+  if (p->two_stage_mask & 8) {
+    y4.ra = yra;
+    y4.rb = yrb;
+  }
   if (y4.ra) y4.nl = kYTwoStageLines;
   y4.u_lo = io.z_lo;
   y4.u_hi = io.z_hi;
@@ -784,6 +830,17 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   }
   x5.nthreads = p->x5threads;
   x5.fft = line_fft<T>(p->ax);
+  if (p->two_stage_mask & 16) {
+    x5.ra = xra;
+    x5.rb = xrb;
+  }
+  if (x5.ra) {
+    x5.ty = 2 * kXTwoStageLines;
+    x5.ytiles = (io.y_hi - io.y_lo + x5.ty - 1) / x5.ty;
+    x5.ntiles = 6 * (io.z_hi - io.z_lo) * x5.ytiles;
+    x5.fd_ytiles = make_fastdiv(x5.ytiles);
+    x5.fd_nc = make_fastdiv(x5.ty / 2);
+  }
 }
 
 template <typename T>
@@ -896,6 +953,7 @@ void set_radices(LineSchedule* s, const std::vector<int>& r) {
 struct TuneEntry {
   std::vector<int> radix;
   int tile = 0;
+  int kern = -1;  // two-stage kernel bits (psatd_plan::two_stage_mask) of the axis's passes, -1 unknown
 };
 std::map<std::string, TuneEntry>& tune_cache() {
   static std::map<std::string, TuneEntry> c;
@@ -905,7 +963,7 @@ std::map<std::string, TuneEntry>& tune_cache() {
 // Version of the cache file format and of the schedule space it describes (the
 // compiled radices, tile rules and register budget).  Entries of files written
 // under another version are discarded.
-constexpr int kTuneSchema = 2;
+constexpr int kTuneSchema = 3;
 
 bool compiled_radix(int r) {
   for (int k : kRadix)
@@ -1014,12 +1072,18 @@ void load_tune_file(const char* path, int* accepted = nullptr, int* rejected = n
       } while (good && sc.eat(','));
       good = good && sc.eat(']');
     }
-    good = good && sc.eat(',') && sc.str(&field) && field == "tile" && sc.eat(':') && sc.num(&v) && sc.eat('}');
+    good = good && sc.eat(',') && sc.str(&field) && field == "tile" && sc.eat(':') && sc.num(&v);
+    e.tile = (int)std::max(-1LL, std::min(v, 1LL << 20));
+    if (good && sc.eat(',')) {
+      long long kv = -1;
+      good = sc.str(&field) && field == "kern" && sc.eat(':') && sc.num(&kv) && kv >= 0 && kv < 32;
+      e.kern = (int)kv;
+    }
+    good = good && sc.eat('}');
     if (!good) {  // malformed: stop reading
       ++bad;
       break;
     }
-    e.tile = (int)std::max(-1LL, std::min(v, 1LL << 20));
     if (current && e.tile > 0 && valid_radices(e.radix, key_length(key))) {
       tune_cache()[key] = e;
       ++ok;
@@ -1041,7 +1105,8 @@ void save_tune_file(const char* path) {
     std::fprintf(f, "    \"%s\": {\"radix\": [", kv.first.c_str());
     for (size_t j = 0; j < kv.second.radix.size(); ++j)
       std::fprintf(f, "%s%d", j ? ", " : "", kv.second.radix[j]);
-    std::fprintf(f, "], \"tile\": %d}%s\n", kv.second.tile, ++i < tune_cache().size() ? "," : "");
+    std::fprintf(f, "], \"tile\": %d, \"kern\": %d}%s\n", kv.second.tile, std::max(0, kv.second.kern),
+                 ++i < tune_cache().size() ? "," : "");
   }
   std::fprintf(f, "  }\n}\n");
   std::fclose(f);
@@ -1090,6 +1155,63 @@ float time_axis(psatd_plan* p, int ax, int reps, hipStream_t s) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return best;
+}
+
+// Mean milliseconds of `reps` launches of pass `pass` (0..4 = P1..P5) on scratch data.
+template <typename T>
+float time_pass(psatd_plan* p, int pass, int reps, hipStream_t s) {
+  StepIO io{};
+  io.wsA = p->wsA;
+  io.wsB = p->wsB;
+  T* scratch = (T*)p->wsB;
+  for (int f = 0; f < 11; ++f) io.src[f] = scratch;
+  for (int f = 0; f < 6; ++f) io.dst[f] = scratch;
+  io.src_elems = io.dst_elems = p->ncell;
+  io.y_lo = 0;
+  io.y_hi = p->NY;
+  io.z_lo = 0;
+  io.z_hi = p->NZ;
+  StepParams<T> sp;
+  build_step<T>(p, io, sp);
+  if (pass == 4) sp.x5.src = (const cx<T>*)p->wsA;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best = 1e30f;
+  for (int rep = 0; rep < 2; ++rep) {  // first round warms up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) {
+      switch (pass) {
+        case 0: launch_xfwd<T>(sp.x1, s); break;
+        case 1: launch_ypass<T>(sp.y2, 0, s); break;
+        case 2: launch_zpush<T>(sp.z3, p->zthreads, s); break;
+        case 3: launch_ypass<T>(sp.y4, 1, s); break;
+        default: launch_xinv<T>(sp.x5, s); break;
+      }
+    }
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms / reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+// Whether pass `pass` has a two-stage kernel under the plan's current schedules.
+template <typename T>
+bool has_two_stage(psatd_plan* p, int pass) {
+  int ra = 0, rb = 0;
+  const size_t cs = sizeof(cx<T>);
+  if (pass == 0 || pass == 4)
+    two_stage_x_radices(p, cs, &ra, &rb);
+  else if (pass == 1 || pass == 3)
+    two_stage_y_radices(p, cs, &ra, &rb);
+  else
+    two_stage_radices(p, cs, &ra, &rb);
+  return ra > 0;
 }
 
 template <typename T>
@@ -1183,6 +1305,27 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
       p->nl_y = best_e.tile;
     } else {
       p->zthreads = best_e.tile;
+    }
+    // Per pass of this axis, the two-stage kernel or the run-time-schedule one,
+    // whichever is faster on the chosen schedule (a cached choice is reused).
+    {
+      const int passes_of_axis[3][2] = {{0, 4}, {1, 3}, {2, -1}};
+      for (int pass : passes_of_axis[a]) {
+        if (pass < 0) continue;
+        const int bit = 1 << pass;
+        if (!has_two_stage<T>(p, pass)) continue;
+        if (hit != tune_cache().end() && hit->second.kern >= 0) {
+          p->two_stage_mask = (p->two_stage_mask & ~bit) | (hit->second.kern & bit);
+          continue;
+        }
+        p->two_stage_mask |= bit;
+        const float t2 = time_pass<T>(p, pass, 3, s);
+        p->two_stage_mask &= ~bit;
+        const float t1 = time_pass<T>(p, pass, 3, s);
+        if (hipGetLastError() != hipSuccess) continue;
+        if (t2 < t1) p->two_stage_mask |= bit;
+      }
+      best_e.kern = p->two_stage_mask & ((a == 0) ? (1 | 16) : (a == 1) ? (2 | 8) : 4);
     }
     tune_cache()[key] = best_e;
   }
@@ -1458,6 +1601,17 @@ int psatd_plan_query(const psatd_plan* p, int what, long long* value) {
     case PSATD_Q_WORKSPACE_BYTES: *value = (long long)p->bytes; break;
     case PSATD_Q_SPECTRUM_POINTS: *value = p->npts; break;
     case PSATD_Q_Z_COLUMNS: *value = p->zcols; break;
+    case PSATD_Q_TWO_STAGE: {
+      long long m = 0;
+      for (int pass = 0; pass < 5; ++pass)
+        if ((p->two_stage_mask >> pass) & 1) {
+          const bool ok = p->fp64 ? has_two_stage<double>(const_cast<psatd_plan*>(p), pass)
+                                  : has_two_stage<float>(const_cast<psatd_plan*>(p), pass);
+          if (ok) m |= 1LL << pass;
+        }
+      *value = m;
+      break;
+    }
     default: return fail(PSATD_EINVAL, "unknown query %d", what);
   }
   return PSATD_OK;

@@ -26,7 +26,7 @@ PSATD_FP64 = 1
 PSATD_FLAG_STAGGERED = 1
 PSATD_FLAG_NO_WORKSPACE = 2
 
-Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS, Q_Z_COLUMNS = range(7)
+Q_BOX_X, Q_BOX_Y, Q_BOX_Z, Q_PRECISION, Q_WORKSPACE_BYTES, Q_SPECTRUM_POINTS, Q_Z_COLUMNS, Q_TWO_STAGE = range(8)
 
 
 class PlanDesc(ctypes.Structure):

@@ -175,7 +175,7 @@ def test_device_budget_gives_enomem_and_leaks_nothing(lib):
         lib.set_device_budget(None)
 
 
-def _write_cache(path, body, schema=2):
+def _write_cache(path, body, schema=3):
     path.write_text('{\n  "psatd_tune_cache": %d,\n  "entries": {\n%s\n  }\n}\n' % (schema, body))
     return str(path)
 
@@ -184,15 +184,20 @@ def test_tune_cache_reader_rejects_stale_and_corrupt_entries(lib, tmp_path):
     good = '    "fp32|x|n=576|m=576|other=320x320": {"radix": [24, 24], "tile": 16}'
     entries = [
         good,
+        '    "fp32|z|n=320|m=320|other=576x320": {"radix": [20, 16], "tile": 256, "kern": 4}',
+        '    "fp32|y|n=320|m=320|other=320x576": {"radix": [20, 16], "tile": 16, "kern": 99}',  # bad kernel bits
         '    "fp32|y|n=320|m=320|other=320x576": {"radix": [16, 16], "tile": 16}',   # product 256 != 320
         '    "fp32|z|n=19|m=19|other=8x8": {"radix": [19], "tile": 256}',           # radix 19 not compiled
         '    "fp32|z|n=320|m=320|other=8x8": {"radix": [], "tile": 256}',           # empty schedule
         '    "fp32|y|n=64|m=64|other=8x8": {"radix": [8, 8], "tile": -3}',          # bad tile
         '    "fp32|y|n=64|len=64": {"radix": [8, 8], "tile": 4}',                    # key without a length
     ]
-    assert lib.tune_cache_load(_write_cache(tmp_path / "a.json", ",\n".join(entries))) == (1, 5)
+    # reading stops at the bad kernel bits: good + the "kern" entry accepted, the rest unread
+    assert lib.tune_cache_load(_write_cache(tmp_path / "a.json", ",\n".join(entries))) == (2, 1)
+    del entries[2]
+    assert lib.tune_cache_load(_write_cache(tmp_path / "a2.json", ",\n".join(entries))) == (2, 5)
     # another schema version: every entry is discarded
-    assert lib.tune_cache_load(_write_cache(tmp_path / "b.json", good, schema=1)) == (0, 1)
+    assert lib.tune_cache_load(_write_cache(tmp_path / "b.json", good, schema=2)) == (0, 1)
     # malformed text: reading stops, nothing after the break is taken
     bad = good + ',\n    "fp32|x|n=64|m=64|other=8x8": {"radix": [8, 8 "tile": 4}'
     assert lib.tune_cache_load(_write_cache(tmp_path / "c.json", bad)) == (1, 1)
