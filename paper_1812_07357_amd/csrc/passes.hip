@@ -203,10 +203,15 @@ __device__ __forceinline__ void xfwd_two_stage_body(const XFwdParams<T>& p) {
   constexpr int N = RA * RB, PA = RA | 1, LD = two_stage_slots(RA, RB);
   cx<T>* lds = lds_base<T>();
   int* xoff = reinterpret_cast<int*>(lds + NL * LD);  // source column of each box x (G1 wrap applied)
+  // stage B twiddles w^(t k), copied once per launch to LDS as [t - 1][k], after the column table
+  Tw<T>* twl = reinterpret_cast<Tw<T>*>(xoff + ((RA * RB + 3) & ~3));
+  for (int i = threadIdx.x; i < RA * (RB - 1); i += NTH) {
+    const int k = i / (RB - 1), t = i - k * (RB - 1);
+    twl[t * RA + k] = p.fft.tw[(RA - 1) + i];
+  }
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTH) xoff[i] = p.gather ? fmod_i(p.x0 + i, p.fd_GX) : i;
   __syncthreads();
-  const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);
   const int NY = p.NY, NXH = p.NXH;
   const int rowlen = p.gather ? p.GX : N;
   for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
@@ -257,10 +262,9 @@ __device__ __forceinline__ void xfwd_two_stage_body(const XFwdParams<T>& p) {
           const cx<T>* y = lds + c * LD + k;
 #pragma unroll
           for (int t = 0; t < RB; ++t) v[u][t] = y[t * PA];
-          const Tw<T>* w = twb + k * (RB - 1) - 1;
           if (k > 0) {
 #pragma unroll
-            for (int t = 1; t < RB; ++t) v[u][t] = twmul<-1>(v[u][t], w[t]);
+            for (int t = 1; t < RB; ++t) v[u][t] = twmul<-1>(v[u][t], twl[(t - 1) * RA + k]);
           }
           dft<RB, -1, T>::run(v[u]);
         }
@@ -303,8 +307,13 @@ template <typename T, int RA, int RB, int NL, int NTH>
 __device__ __forceinline__ void xinv_two_stage_body(const XInvParams<T>& p) {
   constexpr int N = RA * RB, PA = RA | 1, LD = two_stage_slots(RA, RB);
   cx<T>* lds = lds_base<T>();
+  // stage B twiddles w^(t k), copied once per launch to LDS as [t - 1][k]
+  Tw<T>* twl = reinterpret_cast<Tw<T>*>(lds + NL * LD);
+  for (int i = threadIdx.x; i < RA * (RB - 1); i += NTH) {
+    const int k = i / (RB - 1), t = i - k * (RB - 1);
+    twl[t * RA + k] = p.fft.tw[(RA - 1) + i];
+  }
   const int tid = threadIdx.x;
-  const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);
   const int NY = p.NY, NXH = p.NXH;
   for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
     const int q = fdiv(tile, p.fd_ytiles);
@@ -384,10 +393,9 @@ __device__ __forceinline__ void xinv_two_stage_body(const XInvParams<T>& p) {
           const cx<T>* y = lds + c * LD + k;
 #pragma unroll
           for (int t = 0; t < RB; ++t) v[u][t] = y[t * PA];
-          const Tw<T>* w = twb + k * (RB - 1) - 1;
           if (k > 0) {
 #pragma unroll
-            for (int t = 1; t < RB; ++t) v[u][t] = twmul<1>(v[u][t], w[t]);
+            for (int t = 1; t < RB; ++t) v[u][t] = twmul<1>(v[u][t], twl[(t - 1) * RA + k]);
           }
           dft<RB, 1, T>::run(v[u]);
         }
@@ -573,6 +581,17 @@ __device__ __forceinline__ void ypass_two_stage_body(const Src& S) {
   constexpr int PA = G::PA, LD = G::LD;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x;
+  // stage B twiddles w^(t k), copied once per launch to LDS as [t - 1][k]
+  Tw<T>* twl = reinterpret_cast<Tw<T>*>(lds + NL * LD);
+  {
+    int lt0;
+    const YPassParams<T>& p0 = S.box(blockIdx.x, lt0);
+    for (int i = tid; i < RA * (RB - 1); i += NTH) {
+      const int k = i / (RB - 1), t = i - k * (RB - 1);
+      twl[t * RA + k] = p0.fft.tw[(RA - 1) + i];
+    }
+    __syncthreads();
+  }
   for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
     int lt;
     const YPassParams<T>& p = S.box(tile, lt);
@@ -582,7 +601,6 @@ __device__ __forceinline__ void ypass_two_stage_body(const Src& S) {
     const int o = q - f * p.nouter;
     const int u0 = p.u_lo + ut * NL;
     const int nlt = min(NL, p.u_hi - u0);
-    const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);
     // stage A: global -> registers -> DFT -> padded rows
     {
       const rsrc_t in = make_rsrc(p.in + (i64)f * p.fs_in, p.in_bytes);
@@ -620,10 +638,9 @@ __device__ __forceinline__ void ypass_two_stage_body(const Src& S) {
           cx<T> v[RB];
 #pragma unroll
           for (int t = 0; t < RB; ++t) v[t] = y[t * PA];
-          const Tw<T>* w = twb + k * (RB - 1) - 1;
           if (k > 0) {
 #pragma unroll
-            for (int t = 1; t < RB; ++t) v[t] = twmul<S_>(v[t], w[t]);
+            for (int t = 1; t < RB; ++t) v[t] = twmul<S_>(v[t], twl[(t - 1) * RA + k]);
           }
           dft<RB, S_, T>::run(v);
           const bool ok = line < nlt;
@@ -700,13 +717,21 @@ __device__ __forceinline__ void push_point_staggered(const ZPushParams<T>& p, cx
 }
 
 template <typename T>
+__device__ __forceinline__ void push_point_c(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
+                                             int kxi, int kyi, const T* cc);
+template <typename T>
 __device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int col, int kz,
                                            int kxi, int kyi) {
-  const T c2 = p.c2, ie = p.inv_eps0;
   const uint32_t idx = (uint32_t)(col * p.NZ + kz);
   T cc[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) cc[k] = gm<T>::ld(make_rsrc(p.coef + (i64)k * p.npts, p.coef_bytes), idx);
+  push_point_c(p, lds, fs, s, kz, kxi, kyi, cc);
+}
+template <typename T>
+__device__ __forceinline__ void push_point_c(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
+                                             int kxi, int kyi, const T* cc) {
+  const T c2 = p.c2, ie = p.inv_eps0;
   if (p.stag) {
     push_point_staggered(p, lds, fs, s, kz, p.kxc[kxi], p.kyc[kyi], cc);
     return;
@@ -864,10 +889,29 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
   constexpr int N = G::N, PA = G::PA, LD = G::LD;
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x;
+  // stage B twiddles w^(t k), copied once per launch to LDS as [t - 1][k] (lanes take consecutive k)
+  Tw<T>* twl = reinterpret_cast<Tw<T>*>(lds + 11 * LD);
+  {
+    int col0;
+    const ZPushParams<T>& p0 = S.box(blockIdx.x, col0);
+    for (int i = tid; i < RA * (RB - 1); i += NTH) {
+      const int k = i / (RB - 1), t = i - k * (RB - 1);
+      twl[t * RA + k] = p0.fft.tw[(RA - 1) + i];
+    }
+    __syncthreads();
+  }
   for (int tile = blockIdx.x; tile < S.ntiles(); tile += gridDim.x) {
     int col;
     const ZPushParams<T>& p = S.box(tile, col);
-    const Tw<T>* __restrict__ twb = p.fft.tw + (RA - 1);  // stage B twiddles of butterfly k at k (RB - 1)
+    // this thread's push coefficients (points tid and tid + NTH), loaded before the transforms
+    constexpr int NP = (N + NTH - 1) / NTH;
+    T cof[NP][5];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        cof[u][k] = gm<T>::ld(make_rsrc(p.coef + (i64)k * p.npts, p.coef_bytes),
+                              u * NTH + tid < N ? (uint32_t)(col * N + u * NTH + tid) : kOOB);
     // forward stage A: global -> registers -> DFT -> intermediate rows
 #pragma unroll
     for (int b0 = 0; b0 < 11 * RB; b0 += NTH) {
@@ -899,10 +943,9 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
           const cx<T>* y = lds + f * LD + k;
 #pragma unroll
           for (int t = 0; t < RB; ++t) v[u][t] = y[t * PA];
-          const Tw<T>* w = twb + k * (RB - 1) - 1;
           if (k > 0) {
 #pragma unroll
-            for (int t = 1; t < RB; ++t) v[u][t] = twmul<-1>(v[u][t], w[t]);
+            for (int t = 1; t < RB; ++t) v[u][t] = twmul<-1>(v[u][t], twl[(t - 1) * RA + k]);
           }
           dft<RB, -1, T>::run(v[u]);
         }
@@ -924,7 +967,11 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
     {
       const int kxi = fdiv(col, p.fd_NY);
       const int kyi = col - kxi * p.NY;
-      for (int kz = tid; kz < N; kz += NTH) push_point(p, lds, LD, kz, col, kz, kxi, kyi);
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const int kz = u * NTH + tid;
+        if (kz < N) push_point_c(p, lds, LD, kz, kz, kxi, kyi, cof[u]);
+      }
     }
     __syncthreads();
     // inverse stage A on the 6 lines of E and B, from LDS (natural order) back to rows
@@ -965,10 +1012,9 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
         cx<T> v[RB];
 #pragma unroll
         for (int t = 0; t < RB; ++t) v[t] = y[t * PA];
-        const Tw<T>* w = twb + k * (RB - 1) - 1;
         if (k > 0) {
 #pragma unroll
-          for (int t = 1; t < RB; ++t) v[t] = twmul<1>(v[t], w[t]);
+          for (int t = 1; t < RB; ++t) v[t] = twmul<1>(v[t], twl[(t - 1) * RA + k]);
         }
         dft<RB, 1, T>::run(v);
         cx<T>* dst = p.b + (i64)f * p.npts + (i64)col * N + k;
@@ -1218,7 +1264,8 @@ void launch_xfwd_two_stage_at(const XFwdParams<T>& p, hipStream_t s) {
   if constexpr (I < (int)(sizeof(kXTwoStage) / sizeof(kXTwoStage[0]))) {
     constexpr int RA = kXTwoStage[I][0], RB = kXTwoStage[I][1];
     if (p.ra == RA && p.rb == RB) {
-      const size_t lds = (size_t)kXTwoStageLines * two_stage_slots(RA, RB) * cx_bytes<T>() + (size_t)RA * RB * sizeof(int);
+      const size_t lds = (size_t)kXTwoStageLines * two_stage_slots(RA, RB) * cx_bytes<T>() +
+                         (size_t)((RA * RB + 3) & ~3) * sizeof(int) + (size_t)RA * (RB - 1) * sizeof(Tw<T>);
       launch_persistent(k_xfwd2<T, RA, RB>, p, two_stage_x_threads(RA, RB), lds, p.ntiles, s);
       return;
     }
@@ -1230,7 +1277,8 @@ void launch_xinv_two_stage_at(const XInvParams<T>& p, hipStream_t s) {
   if constexpr (I < (int)(sizeof(kXTwoStage) / sizeof(kXTwoStage[0]))) {
     constexpr int RA = kXTwoStage[I][0], RB = kXTwoStage[I][1];
     if (p.ra == RA && p.rb == RB) {
-      const size_t lds = (size_t)kXTwoStageLines * two_stage_slots(RA, RB) * cx_bytes<T>();
+      const size_t lds =
+          (size_t)kXTwoStageLines * two_stage_slots(RA, RB) * cx_bytes<T>() + (size_t)RA * (RB - 1) * sizeof(Tw<T>);
       launch_persistent(k_xinv2<T, RA, RB>, p, two_stage_x_threads(RA, RB), lds, p.ntiles, s);
       return;
     }
@@ -1250,7 +1298,8 @@ void launch_ypass_two_stage_at(const YPassParams<T>& p, int inverse, hipStream_t
   if constexpr (I < (int)(sizeof(kYTwoStage) / sizeof(kYTwoStage[0]))) {
     constexpr int RA = kYTwoStage[I][0], RB = kYTwoStage[I][1];
     if (p.ra == RA && p.rb == RB) {
-      const size_t lds = (size_t)kYTwoStageLines * two_stage_y_slots(RA, RB) * cx_bytes<T>();
+      const size_t lds = (size_t)kYTwoStageLines * two_stage_y_slots(RA, RB) * cx_bytes<T>() +
+                         (size_t)RA * (RB - 1) * sizeof(Tw<T>);
       constexpr int nth = two_stage_y_threads(RA, RB);
       if (inverse)
         launch_persistent(k_ypass2<1, T, RA, RB>, p, nth, lds, p.ntiles, s);
@@ -1284,7 +1333,7 @@ void launch_two_stage_at(const ZPushParams<T>& p, hipStream_t s) {
   if constexpr (I < (int)(sizeof(kZTwoStage) / sizeof(kZTwoStage[0]))) {
     constexpr int RA = kZTwoStage[I][0], RB = kZTwoStage[I][1];
     if (p.ra == RA && p.rb == RB) {
-      const size_t lds = (size_t)11 * two_stage_slots(RA, RB) * cx_bytes<T>();
+      const size_t lds = (size_t)11 * two_stage_slots(RA, RB) * cx_bytes<T>() + (size_t)RA * (RB - 1) * sizeof(Tw<T>);
       launch_persistent(k_zpush2<T, RA, RB>, p, kZTwoStageThreads, lds, p.ntiles, s);
       return;
     }

@@ -565,7 +565,7 @@ void two_stage_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
   if (p->zcols != 1 || p->az.blue || s.nstages != 2) return;
   for (const auto& pr : kZTwoStage)
     if (pr[0] == s.radix[0] && pr[1] == s.radix[1] &&
-        (size_t)11 * two_stage_slots(pr[0], pr[1]) * csize <= lds_limit()) {
+        (size_t)11 * two_stage_slots(pr[0], pr[1]) * csize + (size_t)pr[0] * (pr[1] - 1) * 16 <= lds_limit()) {
       *ra = pr[0];
       *rb = pr[1];
       return;
@@ -581,7 +581,8 @@ void two_stage_x_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
   if (p->ax.blue || s.nstages != 2) return;
   for (const auto& pr : kXTwoStage)
     if (pr[0] == s.radix[0] && pr[1] == s.radix[1] &&
-        (size_t)kXTwoStageLines * two_stage_slots(pr[0], pr[1]) * csize + (size_t)p->NX * sizeof(int) <=
+        (size_t)kXTwoStageLines * two_stage_slots(pr[0], pr[1]) * csize + (size_t)(p->NX + 3) * sizeof(int) +
+                (size_t)pr[0] * (pr[1] - 1) * 16 <=
             lds_limit() / 3) {
       *ra = pr[0];
       *rb = pr[1];
@@ -598,7 +599,8 @@ void two_stage_y_radices(const psatd_plan* p, size_t csize, int* ra, int* rb) {
   if (p->ay.blue || s.nstages != 2) return;
   for (const auto& pr : kYTwoStage)
     if (pr[0] == s.radix[0] && pr[1] == s.radix[1] &&
-        (size_t)kYTwoStageLines * two_stage_y_slots(pr[0], pr[1]) * csize <= lds_limit() / 2) {
+        (size_t)kYTwoStageLines * two_stage_y_slots(pr[0], pr[1]) * csize + (size_t)pr[0] * (pr[1] - 1) * 16 <=
+            lds_limit() / 2) {
       *ra = pr[0];
       *rb = pr[1];
       return;
@@ -1409,14 +1411,23 @@ struct psatd_batch {
   std::vector<std::array<int, 3>> origins;
   void* descs[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // per-pass parameter arrays
   size_t desc_bytes[5] = {0, 0, 0, 0, 0};
-  int* starts = nullptr;                                           // 5 x (nsub + 1) tile offsets
+  int* starts = nullptr;                                           // tile offsets of every launch class
   size_t starts_bytes = 0;
+  // Launch classes of each pass: boxes whose blocks need the same thread count and
+  // a similar LDS size run in one persistent launch sized for them (a box with
+  // long chirp-z lines no longer sets the block shape of every other box).
+  struct Class {
+    int first = 0, nbox = 0;  // boxes [first, first + nbox) of the pass's descriptor array
+    int soff = 0;             // their tile offsets at starts[soff .. soff + nbox]
+    int total = 0;            // tiles
+    int threads = 0;
+    size_t lds = 0;
+  };
+  std::vector<Class> cls[5];
   hipEvent_t done = nullptr;  // completion of the last step / replay (see psatd_plan::done)
   hipStream_t last_stream = nullptr;
   bool in_flight_known = false;
   int totals[5] = {0, 0, 0, 0, 0};
-  size_t lds[5] = {0, 0, 0, 0, 0};
-  int zthreads = 0;
   const void* bound[11] = {};
   bool is_bound = false;
   hipGraph_t graph = nullptr;
@@ -1456,16 +1467,60 @@ int upload(const std::vector<P>& v, void** dst, size_t* dst_bytes) {
   return PSATD_OK;
 }
 
+// LDS a class of batched blocks is sized for: the next of a few fixed sizes.
+size_t lds_bucket(size_t bytes) {
+  static const size_t kb[] = {16, 24, 32, 40, 48, 64, 80, 96, 128, 160};
+  for (size_t v : kb)
+    if (bytes <= v * 1024) return v * 1024;
+  return bytes;
+}
+
+template <typename P>
+void order_pass(const std::vector<P>& in, const std::vector<int>& nt, const std::vector<int>& thr,
+                const std::vector<size_t>& lds, std::vector<P>& out, std::vector<int>& starts,
+                std::vector<psatd_batch::Class>& cls) {
+  const int n = (int)in.size();
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+    return thr[a] != thr[c] ? thr[a] < thr[c] : lds_bucket(lds[a]) < lds_bucket(lds[c]);
+  });
+  out.clear();
+  cls.clear();
+  for (int j = 0; j < n; ++j) {
+    const int i = idx[j];
+    if (cls.empty() || cls.back().threads != thr[i] || lds_bucket(cls.back().lds) != lds_bucket(lds[i])) {
+      psatd_batch::Class c;
+      c.first = j;
+      c.soff = (int)starts.size();
+      c.threads = thr[i];
+      starts.push_back(0);
+      cls.push_back(c);
+    }
+    psatd_batch::Class& c = cls.back();
+    c.nbox += 1;
+    c.total += nt[i];
+    c.lds = std::max(c.lds, lds[i]);
+    starts.push_back(starts.back() + nt[i]);
+    out.push_back(in[i]);
+  }
+}
+
 template <typename T>
 int bind_batch(psatd_batch* b, void* const* g1) {
-  std::vector<XFwdParams<T>> x1(b->nsub);
-  std::vector<YPassParams<T>> y2(b->nsub), y4(b->nsub);
-  std::vector<ZPushParams<T>> z3(b->nsub);
-  std::vector<XInvParams<T>> x5(b->nsub);
-  std::vector<int> starts(5 * (b->nsub + 1), 0);
-  for (int k = 0; k < 5; ++k) b->lds[k] = 0;
-  b->zthreads = 0;
-  for (int i = 0; i < b->nsub; ++i) {
+  const int n = b->nsub;
+  std::vector<XFwdParams<T>> x1(n), x1o;
+  std::vector<YPassParams<T>> y2(n), y4(n), y2o, y4o;
+  std::vector<ZPushParams<T>> z3(n), z3o;
+  std::vector<XInvParams<T>> x5(n), x5o;
+  std::vector<int> nt[5], thr[5];
+  std::vector<size_t> ls[5];
+  for (int k = 0; k < 5; ++k) {
+    nt[k].resize(n);
+    thr[k].resize(n);
+    ls[k].resize(n);
+  }
+  for (int i = 0; i < n; ++i) {
     psatd_plan* p = b->plans[i];
     const StepIO io = g1_io(p, g1, b->origins[i].data(), b->gd);
     StepParams<T> sp;
@@ -1475,19 +1530,29 @@ int bind_batch(psatd_batch* b, void* const* g1) {
     z3[i] = sp.z3;
     y4[i] = sp.y4;
     x5[i] = sp.x5;
-    const int nt[5] = {sp.x1.ntiles, sp.y2.ntiles, sp.z3.ntiles, sp.y4.ntiles, sp.x5.ntiles};
-    const size_t ls[5] = {xfwd_lds(sp.x1), ypass_lds(sp.y2), zpush_lds(sp.z3), ypass_lds(sp.y4), xinv_lds(sp.x5)};
+    const int tiles[5] = {sp.x1.ntiles, sp.y2.ntiles, sp.z3.ntiles, sp.y4.ntiles, sp.x5.ntiles};
+    const int threads[5] = {kLineThreads, kLineThreads, p->zthreads, kLineThreads, p->x5threads};
+    const size_t bytes[5] = {xfwd_lds(sp.x1), ypass_lds(sp.y2), zpush_lds(sp.z3), ypass_lds(sp.y4), xinv_lds(sp.x5)};
     for (int k = 0; k < 5; ++k) {
-      starts[k * (b->nsub + 1) + i + 1] = starts[k * (b->nsub + 1) + i] + nt[k];
-      b->lds[k] = std::max(b->lds[k], ls[k]);
+      nt[k][i] = tiles[k];
+      thr[k][i] = threads[k];
+      ls[k][i] = bytes[k];
     }
-    b->zthreads = std::max(b->zthreads, p->zthreads);
   }
-  for (int k = 0; k < 5; ++k) b->totals[k] = starts[k * (b->nsub + 1) + b->nsub];
+  std::vector<int> starts;
+  order_pass(x1, nt[0], thr[0], ls[0], x1o, starts, b->cls[0]);
+  order_pass(y2, nt[1], thr[1], ls[1], y2o, starts, b->cls[1]);
+  order_pass(z3, nt[2], thr[2], ls[2], z3o, starts, b->cls[2]);
+  order_pass(y4, nt[3], thr[3], ls[3], y4o, starts, b->cls[3]);
+  order_pass(x5, nt[4], thr[4], ls[4], x5o, starts, b->cls[4]);
+  for (int k = 0; k < 5; ++k) {
+    b->totals[k] = 0;
+    for (const auto& c : b->cls[k]) b->totals[k] += c.total;
+  }
   int rc;
-  if ((rc = upload(x1, &b->descs[0], &b->desc_bytes[0])) || (rc = upload(y2, &b->descs[1], &b->desc_bytes[1])) ||
-      (rc = upload(z3, &b->descs[2], &b->desc_bytes[2])) || (rc = upload(y4, &b->descs[3], &b->desc_bytes[3])) ||
-      (rc = upload(x5, &b->descs[4], &b->desc_bytes[4])))
+  if ((rc = upload(x1o, &b->descs[0], &b->desc_bytes[0])) || (rc = upload(y2o, &b->descs[1], &b->desc_bytes[1])) ||
+      (rc = upload(z3o, &b->descs[2], &b->desc_bytes[2])) || (rc = upload(y4o, &b->descs[3], &b->desc_bytes[3])) ||
+      (rc = upload(x5o, &b->descs[4], &b->desc_bytes[4])))
     return rc;
   void* st = b->starts;
   rc = upload(starts, &st, &b->starts_bytes);
@@ -1499,21 +1564,19 @@ int bind_batch(psatd_batch* b, void* const* g1) {
 }
 
 template <typename P>
-BatchArgs<P> batch_args(const psatd_batch* b, int k) {
-  return BatchArgs<P>{(const P*)b->descs[k], b->starts + k * (b->nsub + 1), b->nsub, b->totals[k]};
+BatchArgs<P> class_args(const psatd_batch* b, int k, const psatd_batch::Class& c) {
+  return BatchArgs<P>{(const P*)b->descs[k] + c.first, b->starts + c.soff, c.nbox, c.total};
 }
 
+// One persistent launch per class of every pass; the passes run in order (Jacobi
+// order between the fills and the merges of a step is kept by the pass order).
 template <typename T>
 void enqueue_batch_step(const psatd_batch* b, hipStream_t s) {
-  launch_xfwd_batch<T>(batch_args<XFwdParams<T>>(b, 0), b->lds[0], s);
-  launch_ypass_batch<T>(batch_args<YPassParams<T>>(b, 1), 0, b->lds[1], s);
-  launch_zpush_batch<T>(batch_args<ZPushParams<T>>(b, 2), b->zthreads, b->lds[2], s);
-  launch_ypass_batch<T>(batch_args<YPassParams<T>>(b, 3), 1, b->lds[3], s);
-  // one block size for all boxes: the larger one whenever a box needs it (a
-  // tile fitted for the smaller block also fits the larger)
-  int x5threads = kXInvThreads;
-  for (const psatd_plan* p : b->plans) x5threads = std::max(x5threads, p->x5threads);
-  launch_xinv_batch<T>(batch_args<XInvParams<T>>(b, 4), x5threads, b->lds[4], s);
+  for (const auto& c : b->cls[0]) launch_xfwd_batch<T>(class_args<XFwdParams<T>>(b, 0, c), c.lds, s);
+  for (const auto& c : b->cls[1]) launch_ypass_batch<T>(class_args<YPassParams<T>>(b, 1, c), 0, c.lds, s);
+  for (const auto& c : b->cls[2]) launch_zpush_batch<T>(class_args<ZPushParams<T>>(b, 2, c), c.threads, c.lds, s);
+  for (const auto& c : b->cls[3]) launch_ypass_batch<T>(class_args<YPassParams<T>>(b, 3, c), 1, c.lds, s);
+  for (const auto& c : b->cls[4]) launch_xinv_batch<T>(class_args<XInvParams<T>>(b, 4, c), c.threads, c.lds, s);
 }
 
 int ensure_bound(psatd_batch* b, void* const* g1) {
