@@ -35,8 +35,24 @@ ORDER = 100
 DX = 1.0
 DT = 0.5
 PASSES = ("x_fwd_fill", "y_fwd", "z_push", "y_inv", "x_inv_merge")
-KERNELS = {"x_fwd_fill": "k_xfwd", "y_fwd": "k_ypass<-1>", "z_push": "k_zpush", "y_inv": "k_ypass<1>",
-           "x_inv_merge": "k_xinv"}
+# Kernels of each pass: the run-time-schedule kernel, or the one compiled for the two-stage
+# line schedule (the plan reports which one each pass uses).
+KERNELS = {"x_fwd_fill": ("k_xfwd", "k_xfwd2"), "y_fwd": ("k_ypass<-1>", "k_ypass2<-1>"),
+           "z_push": ("k_zpush", "k_zpush2"), "y_inv": ("k_ypass<1>", "k_ypass2<1>"),
+           "x_inv_merge": ("k_xinv", "k_xinv2")}
+
+
+def pass_of_kernel(name):
+    """The step pass a single-box pass kernel belongs to (None for other kernels)."""
+    import re
+
+    m = re.search(r"k_(xfwd|ypass|zpush|xinv)(2?)(_b)?<(-?1)?", name)
+    if not m or m.group(3):
+        return None
+    kind = m.group(1)
+    if kind == "ypass":
+        return "y_fwd" if m.group(4) == "-1" else "y_inv"
+    return {"xfwd": "x_fwd_fill", "zpush": "z_push", "xinv": "x_inv_merge"}[kind]
 
 
 def log(msg):
@@ -150,7 +166,9 @@ def run_gpu(precision, inputs_host, steps, warmup, staggered=False):
     passes, nrec = plan.pass_times()
     plan.set_timing(False)
     ms = (t1 - t0) * 1e3 / steps
-    res = {"ms_per_step": ms, "passes_ms": passes, "recorded_steps": nrec, "box": plan.box,
+    mask = plan.query(psatd.Q_TWO_STAGE)
+    kernels = {pas: KERNELS[pas][(mask >> i) & 1] for i, pas in enumerate(PASSES)}
+    res = {"ms_per_step": ms, "passes_ms": passes, "recorded_steps": nrec, "box": plan.box, "kernels": kernels,
            "workspace_bytes": plan.query(psatd.Q_WORKSPACE_BYTES), "schedule": schedule}
     fields = g1[0:6].clone()
     plan.close()
@@ -255,8 +273,6 @@ def summarize_pmc(directory, steps, out_json):
     import csv
     import glob
 
-    names = {"k_xfwd<": "x_fwd_fill", "k_ypass<-1": "y_fwd", "k_zpush<": "z_push", "k_ypass<1": "y_inv",
-             "k_xinv<": "x_inv_merge"}
     per = {"FETCH_SIZE": {}, "WRITE_SIZE": {}}
     calib = {}
     for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
@@ -270,9 +286,9 @@ def summarize_pmc(directory, steps, out_json):
                 if "neg_kernel" in k:
                     calib[c] = v
                     continue
-                for key, pas in names.items():
-                    if key in k and "_b<" not in k and "k_xfwd_b" not in k:
-                        per[c].setdefault(pas, []).append((int(r["Dispatch_Id"]), v))
+                pas = pass_of_kernel(k)
+                if pas is not None:
+                    per[c].setdefault(pas, []).append((int(r["Dispatch_Id"]), v))
     if set(calib) != {"FETCH_SIZE", "WRITE_SIZE"}:
         raise SystemExit("calibration kernel (neg) not found in both counter runs")
     gib_kib = float(1 << 20)
@@ -413,7 +429,7 @@ def main():
     achieved = alg[dom] / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(dom, digest),
-                "kernel": KERNELS[dom], "pass": dom, "kernel_ms": round(dom_ms, 4),
+                "kernel": r32["kernels"][dom], "pass": dom, "kernel_ms": round(dom_ms, 4),
                 "algorithmic_bytes_per_launch": alg[dom]}
     step_alg = sum(alg.values())
 
