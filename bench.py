@@ -262,6 +262,82 @@ def run_batch(steps):
             "step_5pass_hbm_frac": round(five / t_graph / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def pic_particles(ppc, u_rms, seed=4):
+    """Cell-ordered warm plasma on the benchmark grid, drawn on the GPU: particle p sits in
+    cell p // ppc (x fastest) at a uniform position inside it, with Gaussian momenta."""
+    import torch
+
+    nx, ny, nz = INTERIOR
+    n = ppc * nx * ny * nz
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    cell = torch.arange(n, device="cuda", dtype=torch.int64) // ppc
+    x = torch.empty((3, n), dtype=torch.float32, device="cuda")
+    x[0] = (cell % nx).float()
+    x[1] = ((cell // nx) % ny).float()
+    x[2] = (cell // (nx * ny)).float()
+    del cell
+    x += torch.rand((3, n), generator=gen, device="cuda")
+    x *= DX
+    top = torch.tensor([nx * DX, ny * DX, nz * DX], device="cuda")[:, None]
+    x = torch.minimum(x, torch.nextafter(top, torch.zeros_like(top)))
+    u = u_rms * torch.randn((3, n), generator=gen, device="cuda")
+    return x.contiguous(), u.contiguous()
+
+
+def run_pic(inputs_host, steps, warmup, ppc=2):
+    """PIC cycle on the benchmark group, FP32: gather + Boris push, deposit through 8^3 D1
+    tiles, the PSATD step on the 576x320x320 FFT box (D2), each timed with HIP events."""
+    import torch
+
+    from paper_1812_07357_amd import psatd
+
+    nx, ny, nz = INTERIOR
+    ncell = nx * ny * nz
+    plan = psatd.Plan(nx, ny, nz, nguard=NGUARD, order=ORDER, dx=DX, dt=DT, precision="fp32")
+    plan.autotune()
+    x, u = pic_particles(ppc, 0.05)
+    n = x.shape[1]
+    pic = psatd.Pic(INTERIOR, dx=DX, dt=DT, q=-0.01 / ppc, q_over_m=-1.0, max_particles=n, tile=8)
+    g1 = torch.as_tensor(inputs_host, dtype=torch.float32).to("cuda")
+    xo = torch.empty_like(x)
+    origin = (0, 0, 0)
+    for _ in range(warmup):
+        pic.push(g1, x, u, xo)
+        pic.deposit(g1, xo, x, u)
+        plan.step_g1(g1, origin)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        pic.push(g1, x, u, xo)
+        ev[k][1].record()
+        pic.deposit(g1, xo, x, u)
+        ev[k][2].record()
+        plan.step_g1(g1, origin)
+        ev[k][3].record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    push = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    dep = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    stp = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+    plan.close()
+    pic.close()
+    del g1, x, u, xo
+    torch.cuda.empty_cache()
+    s = 4
+    # compulsory bytes: push reads x, u and writes x, u, x_old (15 s per particle) and reads E, B once
+    # (6 s per cell); deposit reads x_old, x, u (9 s per particle) and writes J, rho_old, rho_new once
+    push_bytes = 15 * s * n + 6 * s * ncell
+    dep_bytes = 9 * s * n + 5 * s * ncell
+    return {"particles": n, "ppc": ppc, "tile": 8, "ms_per_cycle": ms, "push_ms": round(push, 4),
+            "deposit_ms": round(dep, 4), "maxwell_step_ms": round(stp, 4),
+            "particle_pushes_per_s": n / (ms * 1e-3),
+            "push_hbm_frac": round(push_bytes / (push * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "deposit_hbm_frac": round(dep_bytes / (dep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "cell-ordered warm plasma (u_rms 0.05 c), ppc particles per cell of the 512x256x256 grid"}
+
+
 def summarize_pmc(directory, steps, out_json):
     """HBM traffic per launch of each pass from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this script.
 
@@ -379,6 +455,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-staggered", action="store_true")
+    ap.add_argument("--no-pic", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--extra", action="store_true",
@@ -492,6 +569,10 @@ def main():
         out["staggered_fp32"] = {"value": interior_cells / (rs["ms_per_step"] * 1e-3), "ms_per_step": rs["ms_per_step"],
                                  "passes_ms": {k: round(v, 4) for k, v in rs["passes_ms"].items()},
                                  "note": "same workload on the staggered (Yee) grid, PSATD_FLAG_STAGGERED"}
+
+    if not args.no_pic:
+        log("fp32 PIC cycle (push, deposit, step)")
+        out["pic_fp32"] = run_pic(host, min(args.steps, 20), 2)
 
     if not args.no_batch:
         log("batch run (64 uneven boxes, hipGraph)")

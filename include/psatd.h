@@ -345,6 +345,67 @@ long long psatd_device_bytes_in_use(void);
  * file is not an error (both counts 0). */
 int psatd_tune_cache_load(const char* path, int* accepted, int* rejected);
 
+/* ---------------------------------------------------------------- particles
+ * The particle side of the PIC cycle around the step (Sec. 2.5.1, Fig. 4:
+ * push the particles with the fields at their positions, deposit their current
+ * and charge with linear interpolation, solve Maxwell's equations, gather the
+ * new fields back).  Particle-mesh work runs on the global grid G1 cut into
+ * sub-domains D1 whose guard cells are as wide as the stencil (Sec. 2.5.2):
+ * here a D1 sub-domain is a tile of tile^3 cells handled by one workgroup,
+ * whose guard contributions are added into the neighbouring tiles' cells.
+ *
+ * Grid quantities are the eleven G1 arrays of psatd_step_g1 (gdims cells, x
+ * fastest, slot order Ex Ey Ez Bx By Bz Jx Jy Jz rho_old rho_new), with the
+ * precision of the object.  A quantity with half-cell offsets o (all zero on
+ * the collocated grid; PSATD_FLAG_STAGGERED: the Yee offsets of the plan flag,
+ * J like E, rho on the nodes) has its array index i at (i + o/2) d; the grid is
+ * periodic with lengths L = (gx dx, gy dy, gz dz).  A particle at x takes part
+ * in the 2 x 2 x 2 points around x - o d/2 with the product of the 1D linear
+ * weights (cloud in cell).  Particles are structure-of-arrays: x[0..2] the
+ * positions (x, y, z), u[0..2] the momentum per mass u = gamma v, n values each
+ * (device arrays of the object's precision).  Positions lie in [0, L). */
+typedef struct {
+  int gx, gy, gz;    /* G1 cells */
+  double dx, dy, dz; /* cell sizes (> 0) */
+  double dt, c;      /* time step and speed of light (> 0); c dt <= min(dx, dy, dz) */
+  double q;          /* macro-particle charge */
+  double q_over_m;   /* charge per mass of the species */
+  int max_particles; /* bound on n of every call (>= 0) */
+  int tile;          /* D1 tile edge in cells, 1..16; 8 is a good default */
+  int precision;     /* PSATD_FP32 or PSATD_FP64 */
+  int flags;         /* 0 or PSATD_FLAG_STAGGERED */
+} psatd_pic_desc;
+typedef struct psatd_pic psatd_pic;
+
+/* Checks the descriptor and allocates the per-tile lists (about
+ * 12 bytes per tile + 4 bytes per particle).  PSATD_EUNSUPPORTED if
+ * c dt exceeds the smallest cell size (a particle could then leave its tile's
+ * guard cells within one step) or the tile's LDS block does not fit the
+ * device. */
+int psatd_pic_create(const psatd_pic_desc* desc, psatd_pic** out);
+void psatd_pic_destroy(psatd_pic* pic);
+
+/* Gather and push of n particles: E and B (g1[0..5]) interpolated at x, then the
+ * relativistic Boris step of u (half electric kick, rotation about B at the
+ * mid-step gamma, half kick), then x += dt u / gamma, wrapped into [0, L).
+ * x_old[0..2] receive the positions before the move (for the deposit).  g1
+ * holds the eleven slot pointers; only 0..5 are read.  n = 0 is a no-op
+ * (the particle pointers may then be NULL). */
+int psatd_pic_push(psatd_pic* pic, void* const* g1, void* const* x, void* const* u, void* const* x_old, int n,
+                   void* stream);
+
+/* Deposit of n particles that moved from x_old to x with the half-step u:
+ * g1[6..8] = J = sum q v S(mid-point) / (dx dy dz), v = u / gamma, mid-point
+ * x_old + v dt / 2; g1[9] = rho_old at x_old, g1[10] = rho_new at x, both
+ * sum q S / (dx dy dz).  Slots 6..10 are overwritten (zeroed first, also for
+ * n = 0, when the particle pointers may be NULL); 0..5 are not touched.  The
+ * particles are listed per D1 tile of their start position, each tile
+ * accumulates in LDS over itself and its guard cells, and the block is added
+ * into G1 with atomics: sums are exact up to rounding, whose order varies from
+ * run to run. */
+int psatd_pic_deposit(psatd_pic* pic, void* const* g1, const void* const* x_old, const void* const* x,
+                      const void* const* u, int n, void* stream);
+
 /* Message for the last non-OK return on the calling thread ("" if none). */
 const char* psatd_last_error(void);
 

@@ -1,0 +1,499 @@
+// Particle side of the PIC cycle around the PSATD step (gfx950): field gather +
+// relativistic Boris push, and current / charge deposition through D1 tiles.
+//
+// arXiv:1812.07357, Sec. 2.5.1 (Fig. 4): particles are pushed with the fields at
+// their positions, their current and charge are deposited with linear
+// interpolation, Maxwell's equations are solved, and the fields are gathered
+// back.  Sec. 2.5.2: particle-mesh work runs on the grid G1 split into
+// sub-domains D1 whose guard cells are as wide as the interpolation stencil,
+// while the FFTs run on the boxes of G2 (decomposition D2, psatd_step_g1 /
+// psatd_batch_*), coupled by guard fill and interior copy.
+//
+// Here a D1 sub-domain is a tile of T^3 cells of G1 worked on by one workgroup:
+// the particles are counted per tile (by their start position), the tile
+// offsets scanned, the particles listed per tile, and each workgroup deposits its
+// tile's particles into LDS over the tile plus kPicGuard guard cells per side,
+// then adds that LDS block into G1 (the guard cells land on the neighbouring
+// tiles' cells: the additive guard merge of the D1 decomposition).  The guard
+// width holds the linear stencil of a particle that moved up to one cell during
+// the step, which the host checks (c dt <= min(dx, dy, dz)).
+//
+// Weights: a quantity of a component with half-cell offset o sits at grid point
+// (i + o/2) d; a particle at x spreads over the 2 x 2 x 2 points around it with
+// the product of the 1D linear weights (cloud in cell).  rho = q S / (dx dy dz)
+// at the start and end positions, J = q v S / (dx dy dz) at the mid-point with
+// the half-step velocity.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/psatd.h"
+#include "internal.hpp"
+
+namespace psatd {
+namespace {
+
+constexpr int kPicThreads = 256;
+constexpr int kPicGuard = 2;
+constexpr int kTileMax = 16;
+
+// half-cell offsets of Ex Ey Ez Bx By Bz Jx Jy Jz rho_old rho_new on the staggered grid
+__constant__ int kOffStag[11][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0},
+                                    {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 0, 0}, {0, 0, 0}};
+
+template <typename T>
+struct PicArgs {
+  int gx, gy, gz;
+  T dx, dy, dz;   // cell sizes
+  T idx, idy, idz;  // 1 / cell sizes
+  T lx, ly, lz;   // periodic lengths
+  T dt, c, q, qm;
+  T inv_vol;
+  int stag;
+  int tile, tx, ty, tz, ntiles;  // D1 tiles: edge, tiles per axis, total
+  int n;
+};
+
+// Linear weights of coordinate s (in cells) around grid index i0 = floor(s).
+template <typename T>
+__device__ __forceinline__ void lin(T s, int& i0, T& w1) {
+  const T f = floor(s);
+  i0 = (int)f;
+  w1 = s - f;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Field f interpolated at (x, y, z) (lengths), periodic G1.
+template <typename T>
+__device__ T gather_one(const T* __restrict__ f, const PicArgs<T>& a, int slot, T x, T y, T z) {
+  const int ox = a.stag ? kOffStag[slot][0] : 0, oy = a.stag ? kOffStag[slot][1] : 0,
+            oz = a.stag ? kOffStag[slot][2] : 0;
+  int ix, iy, iz;
+  T wx, wy, wz;
+  lin(x * a.idx - T(0.5) * ox, ix, wx);
+  lin(y * a.idy - T(0.5) * oy, iy, wy);
+  lin(z * a.idz - T(0.5) * oz, iz, wz);
+  T acc = 0;
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz) {
+    const int kz = wrap(iz + cz, a.gz);
+    const T vz = cz ? wz : T(1) - wz;
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      const int ky = wrap(iy + cy, a.gy);
+      const T vy = cy ? wy : T(1) - wy;
+      const long long row = ((long long)kz * a.gy + ky) * a.gx;
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const int kx = wrap(ix + cx, a.gx);
+        const T vx = cx ? wx : T(1) - wx;
+        acc += f[row + kx] * (vx * vy * vz);
+      }
+    }
+  }
+  return acc;
+}
+
+template <typename T>
+struct PushPtrs {
+  const T* f[6];  // Ex Ey Ez Bx By Bz on G1
+  T* x[3];
+  T* u[3];
+  T* x_old[3];
+};
+
+// Gather E, B at x, relativistic Boris push of u = gamma v, x moved by dt u / gamma (wrapped).
+template <typename T>
+__global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs<T> p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const T x = p.x[0][i], y = p.x[1][i], z = p.x[2][i];
+  T E[3], B[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    E[k] = gather_one(p.f[k], a, k, x, y, z);
+    B[k] = gather_one(p.f[3 + k], a, 3 + k, x, y, z);
+  }
+  const T h = T(0.5) * a.qm * a.dt;
+  const T ic2 = T(1) / (a.c * a.c);
+  T um[3] = {p.u[0][i] + h * E[0], p.u[1][i] + h * E[1], p.u[2][i] + h * E[2]};
+  const T gm = sqrt(T(1) + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]) * ic2);
+  const T t[3] = {h * B[0] / gm, h * B[1] / gm, h * B[2] / gm};
+  const T t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  const T s[3] = {T(2) * t[0] / (T(1) + t2), T(2) * t[1] / (T(1) + t2), T(2) * t[2] / (T(1) + t2)};
+  const T up[3] = {um[0] + um[1] * t[2] - um[2] * t[1], um[1] + um[2] * t[0] - um[0] * t[2],
+                   um[2] + um[0] * t[1] - um[1] * t[0]};
+  const T un[3] = {um[0] + up[1] * s[2] - up[2] * s[1] + h * E[0], um[1] + up[2] * s[0] - up[0] * s[2] + h * E[1],
+                   um[2] + up[0] * s[1] - up[1] * s[0] + h * E[2]};
+  const T gn = sqrt(T(1) + (un[0] * un[0] + un[1] * un[1] + un[2] * un[2]) * ic2);
+  const T L[3] = {a.lx, a.ly, a.lz};
+  const T xs[3] = {x, y, z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T xn = xs[k] + a.dt * un[k] / gn;
+    xn -= L[k] * floor(xn / L[k]);
+    if (xn >= L[k]) xn -= L[k];  // rounding at the upper edge
+    p.x_old[k][i] = xs[k];
+    p.x[k][i] = xn;
+    p.u[k][i] = un[k];
+  }
+}
+
+// D1 tile of a start position.
+template <typename T>
+__device__ __forceinline__ int tile_of(const PicArgs<T>& a, T x, T y, T z) {
+  // clamped, so that a position outside [0, L) cannot index past the tile arrays
+  const int cx = min(max((int)(x * a.idx), 0), a.gx - 1), cy = min(max((int)(y * a.idy), 0), a.gy - 1),
+            cz = min(max((int)(z * a.idz), 0), a.gz - 1);
+  return ((cz / a.tile) * a.ty + cy / a.tile) * a.tx + cx / a.tile;
+}
+
+template <typename T>
+struct DepPtrs {
+  const T* xo[3];
+  const T* xn[3];
+  const T* u[3];
+  T* g[5];  // Jx Jy Jz rho_old rho_new on G1
+  int* count;   // ntiles
+  int* offset;  // ntiles + 1
+  int* cursor;  // ntiles
+  int* list;    // n particle indices, tile by tile
+};
+
+__global__ void k_zero_int(int* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
+}
+
+template <typename T>
+__global__ void k_zero_fields(DepPtrs<T> p, long long ncell) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncell)
+#pragma unroll
+    for (int f = 0; f < 5; ++f) p.g[f][i] = T(0);
+}
+
+template <typename T>
+__global__ void k_tile_count(PicArgs<T> a, DepPtrs<T> p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n) atomicAdd(&p.count[tile_of(a, p.xo[0][i], p.xo[1][i], p.xo[2][i])], 1);
+}
+
+// Exclusive scan of the tile counts by one workgroup (offset[ntiles] = n); cursors start
+// at the offsets.
+__global__ void __launch_bounds__(1024) k_tile_scan(const int* count, int* offset, int* cursor, int ntiles) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int per = (ntiles + nth - 1) / nth;
+  const int lo = min(ntiles, tid * per), hi = min(ntiles, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += count[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < nth; d <<= 1) {  // inclusive scan of the per-thread sums
+    const int v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;
+  for (int i = lo; i < hi; ++i) {
+    offset[i] = run;
+    cursor[i] = run;
+    run += count[i];
+  }
+  if (tid == nth - 1) offset[ntiles] = part[nth - 1];
+}
+
+template <typename T>
+__global__ void k_tile_list(PicArgs<T> a, DepPtrs<T> p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n) p.list[atomicAdd(&p.cursor[tile_of(a, p.xo[0][i], p.xo[1][i], p.xo[2][i])], 1)] = i;
+}
+
+// Adds value * linear weights of (x, y, z) for component slot into the LDS block of the
+// tile whose first cell is (bx, by, bz); the block spans E = T + 2 kPicGuard cells per axis.
+template <typename T>
+__device__ __forceinline__ void spread(T* blk, int E, const PicArgs<T>& a, int slot, T x, T y, T z, T value, int bx,
+                                       int by, int bz) {
+  const int ox = a.stag ? kOffStag[slot][0] : 0, oy = a.stag ? kOffStag[slot][1] : 0,
+            oz = a.stag ? kOffStag[slot][2] : 0;
+  int ix, iy, iz;
+  T wx, wy, wz;
+  lin(x * a.idx - T(0.5) * ox, ix, wx);
+  lin(y * a.idy - T(0.5) * oy, iy, wy);
+  lin(z * a.idz - T(0.5) * oz, iz, wz);
+  // local indices relative to the block origin (tile origin - guard); positions near the
+  // periodic edge are taken on the tile's side of the edge.  For positions in [0, L) whose
+  // particle started in the tile the index lies in [0, T + 2]; the clamp only keeps
+  // positions that break that contract inside the block.
+  auto local = [&](int i, int b, int n) {
+    int l = i - (b - kPicGuard);
+    if (l < 0) l += n;
+    if (l >= n) l -= n;
+    return min(max(l, 0), E - 2);
+  };
+  const int lx0 = local(ix, bx, a.gx), ly0 = local(iy, by, a.gy), lz0 = local(iz, bz, a.gz);
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz) {
+    const T vz = cz ? wz : T(1) - wz;
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      const T vy = cy ? wy : T(1) - wy;
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const T vx = cx ? wx : T(1) - wx;
+        const int l = ((lz0 + cz) * E + (ly0 + cy)) * E + (lx0 + cx);
+        atomicAdd(&blk[l], value * (vx * vy * vz));
+      }
+    }
+  }
+}
+
+// One workgroup per D1 tile: its particles' J (mid-point), rho_old (start) and rho_new
+// (end) into LDS over the tile and its guard cells, then the block added into G1.
+template <typename T>
+__global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, DepPtrs<T> p) {
+  extern __shared__ double2 pic_smem[];
+  T* lds = reinterpret_cast<T*>(pic_smem);
+  const int E = a.tile + 2 * kPicGuard;
+  const int ncl = E * E * E;
+  const int tid = threadIdx.x;
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const int tz = t / (a.tx * a.ty), rem = t - tz * a.tx * a.ty, ty = rem / a.tx, tx = rem - ty * a.tx;
+    const int bx = tx * a.tile, by = ty * a.tile, bz = tz * a.tile;
+    for (int i = tid; i < 5 * ncl; i += blockDim.x) lds[i] = T(0);
+    __syncthreads();
+    const T ic2 = T(1) / (a.c * a.c);
+    for (int e = p.offset[t] + tid; e < p.offset[t + 1]; e += blockDim.x) {
+      const int i = p.list[e];
+      const T u0 = p.u[0][i], u1 = p.u[1][i], u2 = p.u[2][i];
+      const T ig = T(1) / sqrt(T(1) + (u0 * u0 + u1 * u1 + u2 * u2) * ic2);
+      const T v[3] = {u0 * ig, u1 * ig, u2 * ig};
+      const T x0 = p.xo[0][i], y0 = p.xo[1][i], z0 = p.xo[2][i];
+      // mid-point (unwrapped from the start position; spread() folds the periodic edge)
+      T xm = x0 + T(0.5) * a.dt * v[0], ym = y0 + T(0.5) * a.dt * v[1], zm = z0 + T(0.5) * a.dt * v[2];
+      xm -= a.lx * floor(xm / a.lx);
+      ym -= a.ly * floor(ym / a.ly);
+      zm -= a.lz * floor(zm / a.lz);
+      const T qv = a.q * a.inv_vol;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) spread(lds + k * ncl, E, a, 6 + k, xm, ym, zm, qv * v[k], bx, by, bz);
+      spread(lds + 3 * ncl, E, a, 9, x0, y0, z0, qv, bx, by, bz);
+      spread(lds + 4 * ncl, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
+    }
+    __syncthreads();
+    // the block (tile and guards) added into G1: guard cells are the neighbours' cells
+    for (int e = tid; e < 5 * ncl; e += blockDim.x) {
+      const T v = lds[e];
+      if (v == T(0)) continue;
+      const int f = e / ncl, l = e - f * ncl;
+      const int lz = l / (E * E), ly = (l / E) % E, lx = l % E;
+      const int gxi = wrap(bx - kPicGuard + lx, a.gx), gyi = wrap(by - kPicGuard + ly, a.gy),
+                gzi = wrap(bz - kPicGuard + lz, a.gz);
+      unsafeAtomicAdd(&p.g[f][((long long)gzi * a.gy + gyi) * a.gx + gxi], v);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+}  // namespace psatd
+
+using namespace psatd;
+
+struct psatd_pic {
+  psatd_pic_desc d{};
+  int fp64 = 0;
+  int tx = 0, ty = 0, tz = 0, ntiles = 0;
+  int* count = nullptr;
+  int* offset = nullptr;
+  int* cursor = nullptr;
+  int* list = nullptr;
+};
+
+namespace {
+
+template <typename T>
+PicArgs<T> pic_args(const psatd_pic* o, int n) {
+  PicArgs<T> a{};
+  const psatd_pic_desc& d = o->d;
+  a.gx = d.gx;
+  a.gy = d.gy;
+  a.gz = d.gz;
+  a.dx = T(d.dx);
+  a.dy = T(d.dy);
+  a.dz = T(d.dz);
+  a.idx = T(1.0 / d.dx);
+  a.idy = T(1.0 / d.dy);
+  a.idz = T(1.0 / d.dz);
+  a.lx = T(d.gx * d.dx);
+  a.ly = T(d.gy * d.dy);
+  a.lz = T(d.gz * d.dz);
+  a.dt = T(d.dt);
+  a.c = T(d.c);
+  a.q = T(d.q);
+  a.qm = T(d.q_over_m);
+  a.inv_vol = T(1.0 / (d.dx * d.dy * d.dz));
+  a.stag = (d.flags & PSATD_FLAG_STAGGERED) ? 1 : 0;
+  a.tile = d.tile;
+  a.tx = o->tx;
+  a.ty = o->ty;
+  a.tz = o->tz;
+  a.ntiles = o->ntiles;
+  a.n = n;
+  return a;
+}
+
+// LDS of one deposit workgroup: five quantities over the tile and its guard cells.
+size_t pic_lds_bytes(int tile, size_t real) {
+  const size_t e = (size_t)tile + 2 * kPicGuard;
+  return 5 * e * e * e * real;
+}
+
+unsigned blocks_for(long long n, int th) { return (unsigned)((n + th - 1) / th); }
+
+template <typename T>
+int pic_push(psatd_pic* o, void* const* g1, void* const* x, void* const* u, void* const* x_old, int n,
+             hipStream_t s) {
+  if (n == 0) return PSATD_OK;
+  PushPtrs<T> p{};
+  for (int k = 0; k < 6; ++k) p.f[k] = (const T*)g1[k];
+  for (int k = 0; k < 3; ++k) {
+    p.x[k] = (T*)x[k];
+    p.u[k] = (T*)u[k];
+    p.x_old[k] = (T*)x_old[k];
+  }
+  hipLaunchKernelGGL(k_pic_push<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, pic_args<T>(o, n), p);
+  return PSATD_OK;
+}
+
+template <typename T>
+int pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const void* const* x, const void* const* u,
+                int n, hipStream_t s) {
+  DepPtrs<T> p{};
+  for (int k = 0; k < 3; ++k) {
+    p.xo[k] = (const T*)x_old[k];
+    p.xn[k] = (const T*)x[k];
+    p.u[k] = (const T*)u[k];
+  }
+  for (int f = 0; f < 5; ++f) p.g[f] = (T*)g1[6 + f];
+  p.count = o->count;
+  p.offset = o->offset;
+  p.cursor = o->cursor;
+  p.list = o->list;
+  const PicArgs<T> a = pic_args<T>(o, n);
+  const long long ncell = (long long)o->d.gx * o->d.gy * o->d.gz;
+  hipLaunchKernelGGL(k_zero_fields<T>, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, p, ncell);
+  if (n == 0) return PSATD_OK;
+  hipLaunchKernelGGL(k_zero_int, dim3(blocks_for(o->ntiles, 256)), dim3(256), 0, s, o->count, o->ntiles);
+  hipLaunchKernelGGL(k_tile_count<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, o->count, o->offset, o->cursor, o->ntiles);
+  hipLaunchKernelGGL(k_tile_list<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
+  const size_t lds = pic_lds_bytes(o->d.tile, sizeof(T));
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_deposit_tiles<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const unsigned grid = (unsigned)std::min(o->ntiles, 4096);
+  hipLaunchKernelGGL(k_deposit_tiles<T>, dim3(grid), dim3(kPicThreads), lds, s, a, p);
+  return PSATD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int psatd_pic_create(const psatd_pic_desc* d, psatd_pic** out) {
+  if (!out) return report_error(PSATD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d) return report_error(PSATD_EINVAL, "descriptor is NULL");
+  if (d->gx <= 0 || d->gy <= 0 || d->gz <= 0) return report_error(PSATD_EINVAL, "grid sizes must be positive");
+  if (!(d->dx > 0) || !(d->dy > 0) || !(d->dz > 0) || !(d->dt > 0) || !(d->c > 0))
+    return report_error(PSATD_EINVAL, "cell sizes, dt and c must be > 0");
+  if (d->precision != PSATD_FP32 && d->precision != PSATD_FP64) return report_error(PSATD_EINVAL, "unknown precision");
+  if (d->flags & ~PSATD_FLAG_STAGGERED) return report_error(PSATD_EINVAL, "unknown flags 0x%x", d->flags);
+  if (d->tile < 1 || d->tile > kTileMax) return report_error(PSATD_EINVAL, "tile must be in [1, %d]", kTileMax);
+  if (d->max_particles < 0) return report_error(PSATD_EINVAL, "max_particles must be >= 0");
+  if (d->c * d->dt > std::min(d->dx, std::min(d->dy, d->dz)))
+    return report_error(PSATD_EUNSUPPORTED,
+                        "c dt = %g exceeds the smallest cell size: a particle could leave its tile's guard cells",
+                        d->c * d->dt);
+  if ((double)d->gx * d->gy * d->gz >= 2147483647.0) return report_error(PSATD_EUNSUPPORTED, "grid too large");
+  {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0) {
+      (void)hipGetLastError();
+      lim = 64 * 1024;
+    }
+    const size_t need = pic_lds_bytes(d->tile, d->precision == PSATD_FP64 ? 8 : 4);
+    if (need > (size_t)lim)
+      return report_error(PSATD_EUNSUPPORTED, "tile %d needs %zu bytes of LDS per workgroup (limit %d)", d->tile,
+                          need, lim);
+  }
+  psatd_pic* o = new psatd_pic;
+  o->d = *d;
+  o->fp64 = d->precision == PSATD_FP64;
+  o->tx = (d->gx + d->tile - 1) / d->tile;
+  o->ty = (d->gy + d->tile - 1) / d->tile;
+  o->tz = (d->gz + d->tile - 1) / d->tile;
+  o->ntiles = o->tx * o->ty * o->tz;
+  const size_t bytes[4] = {(size_t)o->ntiles * 4, (size_t)(o->ntiles + 1) * 4, (size_t)o->ntiles * 4,
+                           (size_t)std::max(1, d->max_particles) * 4};
+  int** ptrs[4] = {&o->count, &o->offset, &o->cursor, &o->list};
+  for (int k = 0; k < 4; ++k)
+    if (hipMalloc((void**)ptrs[k], bytes[k]) != hipSuccess) {
+      (void)hipGetLastError();
+      for (int j = 0; j < k; ++j) (void)hipFree(*ptrs[j]);
+      delete o;
+      return report_error(PSATD_ENOMEM, "particle workspace allocation failed");
+    }
+  *out = o;
+  return PSATD_OK;
+}
+
+void psatd_pic_destroy(psatd_pic* o) {
+  if (!o) return;
+  for (int* q : {o->count, o->offset, o->cursor, o->list})
+    if (q) (void)hipFree(q);
+  delete o;
+}
+
+int psatd_pic_push(psatd_pic* o, void* const* g1, void* const* x, void* const* u, void* const* x_old, int n,
+                   void* stream) {
+  if (!o || !g1 || !x || !u || !x_old) return report_error(PSATD_EINVAL, "NULL argument");
+  if (n < 0 || n > o->d.max_particles) return report_error(PSATD_EINVAL, "n = %d outside [0, max_particles]", n);
+  if (n == 0) return PSATD_OK;
+  for (int k = 0; k < 6; ++k)
+    if (!g1[k]) return report_error(PSATD_EINVAL, "field pointer %d is NULL", k);
+  for (int k = 0; k < 3; ++k)
+    if (!x[k] || !u[k] || !x_old[k]) return report_error(PSATD_EINVAL, "particle array %d is NULL", k);
+  const int rc = o->fp64 ? pic_push<double>(o, g1, x, u, x_old, n, (hipStream_t)stream)
+                         : pic_push<float>(o, g1, x, u, x_old, n, (hipStream_t)stream);
+  if (rc) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PSATD_OK : report_error(PSATD_EHIP, "psatd_pic_push: %s", hipGetErrorString(e));
+}
+
+int psatd_pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const void* const* x,
+                      const void* const* u, int n, void* stream) {
+  if (!o || !g1 || !x_old || !x || !u) return report_error(PSATD_EINVAL, "NULL argument");
+  if (n < 0 || n > o->d.max_particles) return report_error(PSATD_EINVAL, "n = %d outside [0, max_particles]", n);
+  for (int k = 6; k < 11; ++k)
+    if (!g1[k]) return report_error(PSATD_EINVAL, "field pointer %d is NULL", k);
+  for (int k = 0; n > 0 && k < 3; ++k)
+    if (!x[k] || !u[k] || !x_old[k]) return report_error(PSATD_EINVAL, "particle array %d is NULL", k);
+  const int rc = o->fp64 ? pic_deposit<double>(o, g1, x_old, x, u, n, (hipStream_t)stream)
+                         : pic_deposit<float>(o, g1, x_old, x, u, n, (hipStream_t)stream);
+  if (rc) return rc;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PSATD_OK : report_error(PSATD_EHIP, "psatd_pic_deposit: %s", hipGetErrorString(e));
+}
+
+}  // extern "C"

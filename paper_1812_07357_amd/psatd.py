@@ -40,6 +40,15 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class PicDesc(ctypes.Structure):
+    _fields_ = [
+        ("gx", ctypes.c_int), ("gy", ctypes.c_int), ("gz", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("dt", ctypes.c_double), ("c", ctypes.c_double), ("q", ctypes.c_double), ("q_over_m", ctypes.c_double),
+        ("max_particles", ctypes.c_int), ("tile", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
+    ]
+
+
 class PsatdError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"psatd error {code}: {msg}")
@@ -127,6 +136,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_device_bytes_in_use.argtypes = []
     lib.psatd_tune_cache_load.restype = cint
     lib.psatd_tune_cache_load.argtypes = [ctypes.c_char_p, ip, ip]
+    lib.psatd_pic_create.argtypes = [ctypes.POINTER(PicDesc), ctypes.POINTER(vp)]
+    lib.psatd_pic_create.restype = cint
+    lib.psatd_pic_destroy.argtypes = [vp]
+    lib.psatd_pic_destroy.restype = None
+    lib.psatd_pic_push.argtypes = [vp, vpp, vpp, vpp, vpp, cint, vp]
+    lib.psatd_pic_push.restype = cint
+    lib.psatd_pic_deposit.argtypes = [vp, vpp, vpp, vpp, vpp, cint, vp]
+    lib.psatd_pic_deposit.restype = cint
     lib.psatd_last_error.restype = ctypes.c_char_p
     lib.psatd_last_error.argtypes = []
     return lib
@@ -402,6 +419,75 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.psatd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pic:
+    """Particle side of the PIC cycle on the global grid G1 (psatd_pic_*).
+
+    ``gdims`` = (GX, GY, GZ); ``tile`` the D1 tile edge; particles are
+    (3, n) tensors of positions ``x`` and momenta per mass ``u`` (x, y, z rows),
+    of the object's precision, on the GPU.
+    """
+
+    def __init__(self, gdims, dx=1.0, dt=0.5, c=1.0, q=1.0, q_over_m=1.0, max_particles=1 << 20, tile=8,
+                 precision="fp32", staggered=False):
+        import torch
+
+        d = _triple(dx)
+        desc = PicDesc(int(gdims[0]), int(gdims[1]), int(gdims[2]), float(d[0]), float(d[1]), float(d[2]),
+                       float(dt), float(c), float(q), float(q_over_m), int(max_particles), int(tile),
+                       PSATD_FP64 if precision == "fp64" else PSATD_FP32,
+                       PSATD_FLAG_STAGGERED if staggered else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.psatd_pic_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        self.gdims = tuple(int(v) for v in gdims)
+        self.max_particles = int(max_particles)
+        self.precision = "fp64" if precision == "fp64" else "fp32"
+        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
+
+    def _parts(self, name, t, n=None):
+        if not t.is_cuda or t.dtype != self.dtype or t.dim() != 2 or t.shape[0] != 3:
+            raise ValueError(f"{name}: expected a (3, n) {self.dtype} GPU tensor")
+        if n is not None and t.shape[1] != n:
+            raise ValueError(f"{name}: expected {n} particles, got {t.shape[1]}")
+        rows = [t[k] for k in range(3)]
+        if not all(r.is_contiguous() for r in rows):
+            raise ValueError(f"{name}: rows must be contiguous")
+        return rows
+
+    def _g1(self, g1):
+        f = Plan._split(g1, 11)
+        shape = (self.gdims[2], self.gdims[1], self.gdims[0])
+        for t in f:
+            if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or tuple(t.shape) != shape:
+                raise ValueError(f"g1 arrays must be contiguous {self.dtype} GPU tensors of shape {shape}")
+        return f
+
+    def push(self, g1, x, u, x_old, stream=None):
+        """psatd_pic_push: gather E, B at x, Boris-push u, move x (in place); x_old receives the old x."""
+        n = x.shape[1]
+        xs, us, xo = self._parts("x", x), self._parts("u", u, n), self._parts("x_old", x_old, n)
+        _check(_lib.psatd_pic_push(self._h, _ptrs(self._g1(g1)), _ptrs(xs), _ptrs(us), _ptrs(xo), int(n),
+                                   _stream(stream)))
+
+    def deposit(self, g1, x_old, x, u, stream=None):
+        """psatd_pic_deposit: J (mid-point), rho_old, rho_new into g1 slots 6..10 (overwritten)."""
+        n = x.shape[1]
+        xo, xs, us = self._parts("x_old", x_old, n), self._parts("x", x), self._parts("u", u, n)
+        _check(_lib.psatd_pic_deposit(self._h, _ptrs(self._g1(g1)), _ptrs(xo), _ptrs(xs), _ptrs(us), int(n),
+                                      _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.psatd_pic_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -22,3 +22,4 @@ from .fields import (  # noqa: F401
     uneven_decomposition,
     plane_waves_and_blob,
 )
+from .particles import plasma_particles  # noqa: F401,E402

@@ -206,3 +206,31 @@ def test_tune_cache_reader_rejects_stale_and_corrupt_entries(lib, tmp_path):
     (tmp_path / "e.json").write_text("")
     assert lib.tune_cache_load(str(tmp_path / "e.json")) == (0, 1)
     assert lib.tune_cache_load(str(tmp_path / "missing.json")) == (0, 0)
+
+
+def _pic_desc(lib, **kw):
+    d = dict(gx=16, gy=16, gz=16, dx=1.0, dy=1.0, dz=1.0, dt=0.5, c=1.0, q=1.0, q_over_m=1.0, max_particles=100,
+             tile=8, precision=0, flags=0)
+    d.update(kw)
+    return lib.PicDesc(**d)
+
+
+@pytest.mark.parametrize("bad,code", [(dict(gx=0), "EINVAL"), (dict(dz=0.0), "EINVAL"), (dict(dt=-0.5), "EINVAL"),
+                                      (dict(c=0.0), "EINVAL"), (dict(precision=3), "EINVAL"),
+                                      (dict(flags=2), "EINVAL"), (dict(tile=0), "EINVAL"), (dict(tile=17), "EINVAL"),
+                                      (dict(max_particles=-1), "EINVAL"), (dict(dt=1.5), "EUNSUPPORTED"),
+                                      (dict(dy=0.4), "EUNSUPPORTED")])
+def test_pic_descriptors_are_checked_on_the_host(lib, bad, code):
+    h = ctypes.c_void_p()
+    rc = lib._lib.psatd_pic_create(ctypes.byref(_pic_desc(lib, **bad)), ctypes.byref(h))
+    assert rc == getattr(lib, "PSATD_" + code)
+    assert h.value is None
+    assert lib._lib.psatd_last_error().decode() != ""
+
+
+def test_pic_null_arguments(lib):
+    L = lib._lib
+    assert L.psatd_pic_create(None, None) == lib.PSATD_EINVAL
+    assert L.psatd_pic_push(None, None, None, None, None, 0, None) == lib.PSATD_EINVAL
+    assert L.psatd_pic_deposit(None, None, None, None, None, 0, None) == lib.PSATD_EINVAL
+    L.psatd_pic_destroy(None)  # NULL-safe
