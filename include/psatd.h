@@ -367,7 +367,7 @@ int psatd_tune_cache_load(const char* path, int* accepted, int* rejected);
 typedef struct {
   int gx, gy, gz;    /* G1 cells */
   double dx, dy, dz; /* cell sizes (> 0) */
-  double dt, c;      /* time step and speed of light (> 0); c dt <= min(dx, dy, dz) */
+  double dt, c;      /* time step and speed of light (> 0); c dt <= 0.999 min(dx, dy, dz) */
   double q;          /* macro-particle charge */
   double q_over_m;   /* charge per mass of the species */
   int max_particles; /* bound on n of every call (>= 0) */
@@ -377,11 +377,13 @@ typedef struct {
 } psatd_pic_desc;
 typedef struct psatd_pic psatd_pic;
 
-/* Checks the descriptor and allocates the per-tile lists (about
- * 12 bytes per tile + 4 bytes per particle).  PSATD_EUNSUPPORTED if
- * c dt exceeds the smallest cell size (a particle could then leave its tile's
- * guard cells within one step) or the tile's LDS block does not fit the
- * device. */
+/* Checks the descriptor and allocates the per-tile lists (12 bytes per tile
+ * + 4 bytes per particle).  A tile accumulates over itself, one guard cell
+ * below and two above per axis: the reach of the linear stencil of a particle
+ * that started in the tile and moved less than a cell.  PSATD_EUNSUPPORTED if
+ * c dt exceeds 0.999 of the smallest cell size (a particle could then leave
+ * those guard cells within one step; the margin absorbs the rounding of
+ * positions) or the tile's LDS block does not fit the device. */
 int psatd_pic_create(const psatd_pic_desc* desc, psatd_pic** out);
 void psatd_pic_destroy(psatd_pic* pic);
 

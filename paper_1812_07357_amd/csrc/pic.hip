@@ -12,11 +12,12 @@
 // Here a D1 sub-domain is a tile of T^3 cells of G1 worked on by one workgroup:
 // the particles are counted per tile (by their start position), the tile
 // offsets scanned, the particles listed per tile, and each workgroup deposits its
-// tile's particles into LDS over the tile plus kPicGuard guard cells per side,
-// then adds that LDS block into G1 (the guard cells land on the neighbouring
-// tiles' cells: the additive guard merge of the D1 decomposition).  The guard
-// width holds the linear stencil of a particle that moved up to one cell during
-// the step, which the host checks (c dt <= min(dx, dy, dz)).
+// tile's particles into LDS over the tile plus its guard cells (kGuardLo below,
+// kGuardHi above, per axis), then adds that LDS block into G1 (the guard cells land
+// on the neighbouring tiles' cells: the additive guard merge of the D1
+// decomposition).  The guards hold the linear stencil of a particle that started in
+// the tile and moved less than one cell during the step, which the host ensures
+// (c dt below the smallest cell size, with a margin for rounding).
 //
 // Weights: a quantity of a component with half-cell offset o sits at grid point
 // (i + o/2) d; a particle at x spreads over the 2 x 2 x 2 points around it with
@@ -37,7 +38,12 @@ namespace psatd {
 namespace {
 
 constexpr int kPicThreads = 256;
-constexpr int kPicGuard = 2;
+// Stencil reach of a particle that starts in cell c and moves less than one cell: the
+// points of rho_new and of J (mid-point, half a cell away) span [c - 1, c + 2].
+constexpr int kGuardLo = 1;
+constexpr int kGuardHi = 2;
+// c dt may reach this fraction of the smallest cell (the rest absorbs rounding).
+constexpr double kMaxCourant = 0.999;
 constexpr int kTileMax = 16;
 
 // half-cell offsets of Ex Ey Ez Bx By Bz Jx Jy Jz rho_old rho_new on the staggered grid
@@ -180,10 +186,37 @@ __global__ void k_zero_fields(DepPtrs<T> p, long long ncell) {
     for (int f = 0; f < 5; ++f) p.g[f][i] = T(0);
 }
 
+// Runs of equal keys in consecutive lanes of a wave: whether this lane leads its run,
+// the run's leading lane and (at the leader) its length.  Inactive lanes carry
+// distinct keys, so they never join a run.  Every lane of the wave must call it.
+struct WaveRun {
+  bool head;
+  int leader, len;
+};
+__device__ __forceinline__ WaveRun wave_run(int key, bool active) {
+  const int lane = __lane_id();
+  const int k = active ? key : -1 - lane;
+  const int prev = __shfl_up(k, 1);
+  const bool head = lane == 0 || prev != k;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane (all for lane 63)
+  const unsigned long long after = heads & ~upto;
+  WaveRun r;
+  r.head = head;
+  r.leader = 63 - __clzll(heads & upto);
+  r.len = (after ? __ffsll((long long)after) - 1 : 64) - lane;
+  return r;
+}
+
+// Particles per D1 tile; particles of one tile in consecutive lanes (cell-ordered
+// input) add their count with one atomic per run.
 template <typename T>
-__global__ void k_tile_count(PicArgs<T> a, DepPtrs<T> p) {
+__global__ void __launch_bounds__(kPicThreads) k_tile_count(PicArgs<T> a, DepPtrs<T> p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n) atomicAdd(&p.count[tile_of(a, p.xo[0][i], p.xo[1][i], p.xo[2][i])], 1);
+  const bool active = i < a.n;
+  const int t = active ? tile_of(a, p.xo[0][i], p.xo[1][i], p.xo[2][i]) : 0;
+  const WaveRun r = wave_run(t, active);
+  if (active && r.head) atomicAdd(&p.count[t], r.len);
 }
 
 // Exclusive scan of the tile counts by one workgroup (offset[ntiles] = n); cursors start
@@ -212,14 +245,22 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const int* count, int* offse
   if (tid == nth - 1) offset[ntiles] = part[nth - 1];
 }
 
+// Particle indices listed tile by tile: a run of one tile's particles in consecutive
+// lanes takes its slots with one atomic and fills them in lane order.
 template <typename T>
-__global__ void k_tile_list(PicArgs<T> a, DepPtrs<T> p) {
+__global__ void __launch_bounds__(kPicThreads) k_tile_list(PicArgs<T> a, DepPtrs<T> p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n) p.list[atomicAdd(&p.cursor[tile_of(a, p.xo[0][i], p.xo[1][i], p.xo[2][i])], 1)] = i;
+  const bool active = i < a.n;
+  const int t = active ? tile_of(a, p.xo[0][i], p.xo[1][i], p.xo[2][i]) : 0;
+  const WaveRun r = wave_run(t, active);
+  int base = 0;
+  if (active && r.head) base = atomicAdd(&p.cursor[t], r.len);
+  base = __shfl(base, r.leader);
+  if (active) p.list[base + (int)__lane_id() - r.leader] = i;
 }
 
 // Adds value * linear weights of (x, y, z) for component slot into the LDS block of the
-// tile whose first cell is (bx, by, bz); the block spans E = T + 2 kPicGuard cells per axis.
+// tile whose first cell is (bx, by, bz); the block spans E = T + kGuardLo + kGuardHi cells per axis.
 template <typename T>
 __device__ __forceinline__ void spread(T* blk, int E, const PicArgs<T>& a, int slot, T x, T y, T z, T value, int bx,
                                        int by, int bz) {
@@ -232,10 +273,10 @@ __device__ __forceinline__ void spread(T* blk, int E, const PicArgs<T>& a, int s
   lin(z * a.idz - T(0.5) * oz, iz, wz);
   // local indices relative to the block origin (tile origin - guard); positions near the
   // periodic edge are taken on the tile's side of the edge.  For positions in [0, L) whose
-  // particle started in the tile the index lies in [0, T + 2]; the clamp only keeps
+  // particle started in the tile the index lies in [0, T + 1]; the clamp only keeps
   // positions that break that contract inside the block.
   auto local = [&](int i, int b, int n) {
-    int l = i - (b - kPicGuard);
+    int l = i - (b - kGuardLo);
     if (l < 0) l += n;
     if (l >= n) l -= n;
     return min(max(l, 0), E - 2);
@@ -263,9 +304,12 @@ template <typename T>
 __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, DepPtrs<T> p) {
   extern __shared__ double2 pic_smem[];
   T* lds = reinterpret_cast<T*>(pic_smem);
-  const int E = a.tile + 2 * kPicGuard;
+  const int E = a.tile + kGuardLo + kGuardHi;
   const int ncl = E * E * E;
   const int tid = threadIdx.x;
+  // merge walk: thread (row r0, column lx) of R = blockDim / E rows per round
+  const int R = blockDim.x / E, r0 = tid / E, lx = tid - r0 * E;
+  const int dy = R % E, dz = (R / E) % E, df = R / (E * E);
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const int tz = t / (a.tx * a.ty), rem = t - tz * a.tx * a.ty, ty = rem / a.tx, tx = rem - ty * a.tx;
     const int bx = tx * a.tile, by = ty * a.tile, bz = tz * a.tile;
@@ -290,15 +334,37 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
       spread(lds + 4 * ncl, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
     }
     __syncthreads();
-    // the block (tile and guards) added into G1: guard cells are the neighbours' cells
-    for (int e = tid; e < 5 * ncl; e += blockDim.x) {
-      const T v = lds[e];
-      if (v == T(0)) continue;
-      const int f = e / ncl, l = e - f * ncl;
-      const int lz = l / (E * E), ly = (l / E) % E, lx = l % E;
-      const int gxi = wrap(bx - kPicGuard + lx, a.gx), gyi = wrap(by - kPicGuard + ly, a.gy),
-                gzi = wrap(bz - kPicGuard + lz, a.gz);
-      unsafeAtomicAdd(&p.g[f][((long long)gzi * a.gy + gyi) * a.gx + gxi], v);
+    // the block (tile and guards) added into G1: guard cells are the neighbours' cells.
+    // Rows (f, z, y) are walked with carries, so no element needs a division.
+    if (r0 < R) {
+      auto wrap_near = [](int v, int n) {  // v in [-n, ...): one add or subtract except on tiny grids
+        if (v < 0) v += n;
+        if (v >= n) {
+          v -= n;
+          if (v >= n) v %= n;
+        }
+        return v;
+      };
+      const int gxi = wrap_near(bx - kGuardLo + lx, a.gx);
+      int y = r0 % E, z = (r0 / E) % E, f = r0 / (E * E);
+      while (f < 5) {
+        const T v = lds[((f * E + z) * E + y) * E + lx];
+        if (v != T(0)) {
+          const int gyi = wrap_near(by - kGuardLo + y, a.gy), gzi = wrap_near(bz - kGuardLo + z, a.gz);
+          unsafeAtomicAdd(&p.g[f][((long long)gzi * a.gy + gyi) * a.gx + gxi], v);
+        }
+        y += dy;
+        if (y >= E) {
+          y -= E;
+          ++z;
+        }
+        z += dz;
+        if (z >= E) {
+          z -= E;
+          ++f;
+        }
+        f += df;
+      }
     }
     __syncthreads();
   }
@@ -354,7 +420,7 @@ PicArgs<T> pic_args(const psatd_pic* o, int n) {
 
 // LDS of one deposit workgroup: five quantities over the tile and its guard cells.
 size_t pic_lds_bytes(int tile, size_t real) {
-  const size_t e = (size_t)tile + 2 * kPicGuard;
+  const size_t e = (size_t)tile + kGuardLo + kGuardHi;
   return 5 * e * e * e * real;
 }
 
@@ -400,7 +466,8 @@ int pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const v
   const size_t lds = pic_lds_bytes(o->d.tile, sizeof(T));
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_deposit_tiles<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const unsigned grid = (unsigned)std::min(o->ntiles, 4096);
+  // one tile per workgroup (the loop inside covers grids beyond the cap)
+  const unsigned grid = (unsigned)std::min(o->ntiles, 1 << 20);
   hipLaunchKernelGGL(k_deposit_tiles<T>, dim3(grid), dim3(kPicThreads), lds, s, a, p);
   return PSATD_OK;
 }
@@ -420,10 +487,11 @@ int psatd_pic_create(const psatd_pic_desc* d, psatd_pic** out) {
   if (d->flags & ~PSATD_FLAG_STAGGERED) return report_error(PSATD_EINVAL, "unknown flags 0x%x", d->flags);
   if (d->tile < 1 || d->tile > kTileMax) return report_error(PSATD_EINVAL, "tile must be in [1, %d]", kTileMax);
   if (d->max_particles < 0) return report_error(PSATD_EINVAL, "max_particles must be >= 0");
-  if (d->c * d->dt > std::min(d->dx, std::min(d->dy, d->dz)))
+  // a particle moves less than c dt per step; the margin covers the rounding of positions
+  if (d->c * d->dt > kMaxCourant * std::min(d->dx, std::min(d->dy, d->dz)))
     return report_error(PSATD_EUNSUPPORTED,
-                        "c dt = %g exceeds the smallest cell size: a particle could leave its tile's guard cells",
-                        d->c * d->dt);
+                        "c dt = %g exceeds %g of the smallest cell size: a particle could leave its tile's guard "
+                        "cells", d->c * d->dt, kMaxCourant);
   if ((double)d->gx * d->gy * d->gz >= 2147483647.0) return report_error(PSATD_EUNSUPPORTED, "grid too large");
   {
     int dev = 0, lim = 0;
