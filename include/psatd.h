@@ -371,7 +371,7 @@ typedef struct {
   double q;          /* macro-particle charge */
   double q_over_m;   /* charge per mass of the species */
   int max_particles; /* bound on n of every call (>= 0) */
-  int tile;          /* D1 tile edge in cells, 1..16; 8 is a good default */
+  int tile;          /* D1 tile edge in cells, 1..12; 8 is a good default */
   int precision;     /* PSATD_FP32 or PSATD_FP64 */
   int flags;         /* 0 or PSATD_FLAG_STAGGERED */
 } psatd_pic_desc;
@@ -402,8 +402,10 @@ int psatd_pic_push(psatd_pic* pic, void* const* g1, void* const* x, void* const*
  * sum q S / (dx dy dz).  Slots 6..10 are overwritten (zeroed first, also for
  * n = 0, when the particle pointers may be NULL); 0..5 are not touched.  The
  * particles are listed per D1 tile of their start position, each tile
- * accumulates in LDS over itself and its guard cells, and the block is added
- * into G1 with atomics: sums are exact up to rounding, whose order varies from
+ * accumulates in LDS over itself and its guard cells in 64-bit fixed point (a
+ * power-of-two scale per tile: exact integer sums of the rounded
+ * contributions, independent of order), and the block is added into G1 with
+ * floating-point atomics, whose order between neighbouring tiles varies from
  * run to run. */
 int psatd_pic_deposit(psatd_pic* pic, void* const* g1, const void* const* x_old, const void* const* x,
                       const void* const* u, int n, void* stream);

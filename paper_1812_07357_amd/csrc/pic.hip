@@ -17,7 +17,9 @@
 // on the neighbouring tiles' cells: the additive guard merge of the D1
 // decomposition).  The guards hold the linear stencil of a particle that started in
 // the tile and moved less than one cell during the step, which the host ensures
-// (c dt below the smallest cell size, with a margin for rounding).
+// (c dt below the smallest cell size, with a margin for rounding).  The LDS block sums in
+// 64-bit fixed point with a power-of-two scale per tile, so a tile's sums are exact and do
+// not depend on the order of the atomics.
 //
 // Weights: a quantity of a component with half-cell offset o sits at grid point
 // (i + o/2) d; a particle at x spreads over the 2 x 2 x 2 points around it with
@@ -44,7 +46,7 @@ constexpr int kGuardLo = 1;
 constexpr int kGuardHi = 2;
 // c dt may reach this fraction of the smallest cell (the rest absorbs rounding).
 constexpr double kMaxCourant = 0.999;
-constexpr int kTileMax = 16;
+constexpr int kTileMax = 12;
 
 // half-cell offsets of Ex Ey Ez Bx By Bz Jx Jy Jz rho_old rho_new on the staggered grid
 __constant__ int kOffStag[11][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0},
@@ -259,11 +261,19 @@ __global__ void __launch_bounds__(kPicThreads) k_tile_list(PicArgs<T> a, DepPtrs
   if (active) p.list[base + (int)__lane_id() - r.leader] = i;
 }
 
-// Adds value * linear weights of (x, y, z) for component slot into the LDS block of the
-// tile whose first cell is (bx, by, bz); the block spans E = T + kGuardLo + kGuardHi cells per axis.
+// The linear stencil of one quantity of one particle inside the LDS block of a tile: the
+// block-local index of its lower corner and the eight weighted values, corners in (z, y, x)
+// order.  The block spans E = T + kGuardLo + kGuardHi cells per axis from the tile's first
+// cell (bx, by, bz) minus kGuardLo.
 template <typename T>
-__device__ __forceinline__ void spread(T* blk, int E, const PicArgs<T>& a, int slot, T x, T y, T z, T value, int bx,
-                                       int by, int bz) {
+struct Stencil {
+  int l0;
+  T w[8];
+};
+
+template <typename T>
+__device__ __forceinline__ void stencil(Stencil<T>& s, int E, const PicArgs<T>& a, int slot, T x, T y, T z,
+                                        T value, int bx, int by, int bz) {
   const int ox = a.stag ? kOffStag[slot][0] : 0, oy = a.stag ? kOffStag[slot][1] : 0,
             oz = a.stag ? kOffStag[slot][2] : 0;
   int ix, iy, iz;
@@ -281,20 +291,40 @@ __device__ __forceinline__ void spread(T* blk, int E, const PicArgs<T>& a, int s
     if (l >= n) l -= n;
     return min(max(l, 0), E - 2);
   };
-  const int lx0 = local(ix, bx, a.gx), ly0 = local(iy, by, a.gy), lz0 = local(iz, bz, a.gz);
+  s.l0 = (local(iz, bz, a.gz) * E + local(iy, by, a.gy)) * E + local(ix, bx, a.gx);
 #pragma unroll
-  for (int cz = 0; cz < 2; ++cz) {
-    const T vz = cz ? wz : T(1) - wz;
+  for (int c = 0; c < 8; ++c) {
+    const T vx = (c & 1) ? wx : T(1) - wx, vy = (c & 2) ? wy : T(1) - wy, vz = (c & 4) ? wz : T(1) - wz;
+    s.w[c] = value * (vx * vy * vz);
+  }
+}
+
+// The LDS block accumulates in 64-bit fixed point: each weighted value times a power of two
+// `scale`, rounded to an integer, added with an integer LDS atomic (floating-point LDS
+// atomics are several times slower).  Integer sums are exact and independent of their order;
+// the scale keeps every sum below 2^62 in magnitude (see k_deposit_tiles).
+using fixed_t = unsigned long long;
+
+template <typename T>
+__device__ __forceinline__ void stencil_add(fixed_t* blk, int E, const Stencil<T>& s, T scale) {
 #pragma unroll
-    for (int cy = 0; cy < 2; ++cy) {
-      const T vy = cy ? wy : T(1) - wy;
+  for (int c = 0; c < 8; ++c) {
+    const long long v = llrint((double)(s.w[c] * scale));
+    atomicAdd(&blk[s.l0 + ((c >> 2) * E + ((c >> 1) & 1)) * E + (c & 1)], (fixed_t)v);
+  }
+}
+
+// Running sum of the stencils of consecutive particles of one thread: particles whose
+// stencil has the same lower corner are summed in registers, and the LDS block receives one
+// set of atomics per run (particles of one cell come in runs when the input is cell-ordered).
+template <typename T>
+__device__ __forceinline__ void stencil_run(fixed_t* blk, int E, Stencil<T>& acc, const Stencil<T>& cur, T scale) {
+  if (cur.l0 == acc.l0) {
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const T vx = cx ? wx : T(1) - wx;
-        const int l = ((lz0 + cz) * E + (ly0 + cy)) * E + (lx0 + cx);
-        atomicAdd(&blk[l], value * (vx * vy * vz));
-      }
-    }
+    for (int c = 0; c < 8; ++c) acc.w[c] += cur.w[c];
+  } else {
+    if (acc.l0 >= 0) stencil_add(blk, E, acc, scale);
+    acc = cur;
   }
 }
 
@@ -303,7 +333,7 @@ __device__ __forceinline__ void spread(T* blk, int E, const PicArgs<T>& a, int s
 template <typename T>
 __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, DepPtrs<T> p) {
   extern __shared__ double2 pic_smem[];
-  T* lds = reinterpret_cast<T*>(pic_smem);
+  fixed_t* lds = reinterpret_cast<fixed_t*>(pic_smem);
   const int E = a.tile + kGuardLo + kGuardHi;
   const int ncl = E * E * E;
   const int tid = threadIdx.x;
@@ -313,26 +343,52 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const int tz = t / (a.tx * a.ty), rem = t - tz * a.tx * a.ty, ty = rem / a.tx, tx = rem - ty * a.tx;
     const int bx = tx * a.tile, by = ty * a.tile, bz = tz * a.tile;
-    for (int i = tid; i < 5 * ncl; i += blockDim.x) lds[i] = T(0);
+    for (int i = tid; i < 5 * ncl; i += blockDim.x) lds[i] = 0;
     __syncthreads();
     const T ic2 = T(1) / (a.c * a.c);
-    for (int e = p.offset[t] + tid; e < p.offset[t + 1]; e += blockDim.x) {
+    const T qv = a.q * a.inv_vol;
+    // each thread takes a contiguous run of the tile's list, so the lanes of a wave work in
+    // different cells (no two lanes add to one LDS word in the same instruction) and one
+    // thread's consecutive particles share stencils
+    const int first = p.offset[t], count = p.offset[t + 1] - first;
+    // fixed-point scales of J and rho: a particle adds at most |q| c / V (|v| < c) to a J
+    // point and |q| / V to a rho point, so with count particles every sum stays below
+    // count * bound * scale < 2^62.  Powers of two: scaling and unscaling are exact.
+    const double bq = fabs((double)a.q) * (double)a.inv_vol * (double)max(count, 1);
+    const int ej = 61 - ilogb(fmax(bq * (double)a.c * 1.0000001, 1e-300));
+    const int er = 61 - ilogb(fmax(bq * 1.0000001, 1e-300));
+    // (capped where the bound is tiny: then bound * 2^120 is below 2^62 anyway)
+    const int ejc = min(ej, 120), erc = min(er, 120);
+    const T sj = (T)ldexp(1.0, ejc), sr = (T)ldexp(1.0, erc);
+    const int per = (count + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int e0 = first + min(count, tid * per), e1 = first + min(count, (tid + 1) * per);
+    Stencil<T> acc[5], cur;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[q].l0 = -1;
+    for (int e = e0; e < e1; ++e) {
       const int i = p.list[e];
       const T u0 = p.u[0][i], u1 = p.u[1][i], u2 = p.u[2][i];
       const T ig = T(1) / sqrt(T(1) + (u0 * u0 + u1 * u1 + u2 * u2) * ic2);
       const T v[3] = {u0 * ig, u1 * ig, u2 * ig};
       const T x0 = p.xo[0][i], y0 = p.xo[1][i], z0 = p.xo[2][i];
-      // mid-point (unwrapped from the start position; spread() folds the periodic edge)
+      // mid-point (unwrapped from the start position; stencil() folds the periodic edge)
       T xm = x0 + T(0.5) * a.dt * v[0], ym = y0 + T(0.5) * a.dt * v[1], zm = z0 + T(0.5) * a.dt * v[2];
       xm -= a.lx * floor(xm / a.lx);
       ym -= a.ly * floor(ym / a.ly);
       zm -= a.lz * floor(zm / a.lz);
-      const T qv = a.q * a.inv_vol;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) spread(lds + k * ncl, E, a, 6 + k, xm, ym, zm, qv * v[k], bx, by, bz);
-      spread(lds + 3 * ncl, E, a, 9, x0, y0, z0, qv, bx, by, bz);
-      spread(lds + 4 * ncl, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
+      for (int k = 0; k < 3; ++k) {
+        stencil(cur, E, a, 6 + k, xm, ym, zm, qv * v[k], bx, by, bz);
+        stencil_run(lds + k * ncl, E, acc[k], cur, sj);
+      }
+      stencil(cur, E, a, 9, x0, y0, z0, qv, bx, by, bz);
+      stencil_run(lds + 3 * ncl, E, acc[3], cur, sr);
+      stencil(cur, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
+      stencil_run(lds + 4 * ncl, E, acc[4], cur, sr);
     }
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      if (acc[q].l0 >= 0) stencil_add(lds + q * ncl, E, acc[q], q < 3 ? sj : sr);
     __syncthreads();
     // the block (tile and guards) added into G1: guard cells are the neighbours' cells.
     // Rows (f, z, y) are walked with carries, so no element needs a division.
@@ -348,8 +404,9 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
       const int gxi = wrap_near(bx - kGuardLo + lx, a.gx);
       int y = r0 % E, z = (r0 / E) % E, f = r0 / (E * E);
       while (f < 5) {
-        const T v = lds[((f * E + z) * E + y) * E + lx];
-        if (v != T(0)) {
+        const long long iv = (long long)lds[((f * E + z) * E + y) * E + lx];
+        if (iv != 0) {
+          const T v = (T)((double)iv * ldexp(1.0, -(f < 3 ? ejc : erc)));
           const int gyi = wrap_near(by - kGuardLo + y, a.gy), gzi = wrap_near(bz - kGuardLo + z, a.gz);
           unsafeAtomicAdd(&p.g[f][((long long)gzi * a.gy + gyi) * a.gx + gxi], v);
         }
@@ -418,10 +475,10 @@ PicArgs<T> pic_args(const psatd_pic* o, int n) {
   return a;
 }
 
-// LDS of one deposit workgroup: five quantities over the tile and its guard cells.
-size_t pic_lds_bytes(int tile, size_t real) {
+// LDS of one deposit workgroup: five fixed-point quantities over the tile and its guard cells.
+size_t pic_lds_bytes(int tile) {
   const size_t e = (size_t)tile + kGuardLo + kGuardHi;
-  return 5 * e * e * e * real;
+  return 5 * e * e * e * sizeof(fixed_t);
 }
 
 unsigned blocks_for(long long n, int th) { return (unsigned)((n + th - 1) / th); }
@@ -463,7 +520,7 @@ int pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const v
   hipLaunchKernelGGL(k_tile_count<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, o->count, o->offset, o->cursor, o->ntiles);
   hipLaunchKernelGGL(k_tile_list<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
-  const size_t lds = pic_lds_bytes(o->d.tile, sizeof(T));
+  const size_t lds = pic_lds_bytes(o->d.tile);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_deposit_tiles<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   // one tile per workgroup (the loop inside covers grids beyond the cap)
@@ -500,7 +557,7 @@ int psatd_pic_create(const psatd_pic_desc* d, psatd_pic** out) {
       (void)hipGetLastError();
       lim = 64 * 1024;
     }
-    const size_t need = pic_lds_bytes(d->tile, d->precision == PSATD_FP64 ? 8 : 4);
+    const size_t need = pic_lds_bytes(d->tile);
     if (need > (size_t)lim)
       return report_error(PSATD_EUNSUPPORTED, "tile %d needs %zu bytes of LDS per workgroup (limit %d)", d->tile,
                           need, lim);
