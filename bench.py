@@ -338,6 +338,39 @@ def run_pic(inputs_host, steps, warmup, ppc=2):
             "note": "cell-ordered warm plasma (u_rms 0.05 c), ppc particles per cell of the 512x256x256 grid"}
 
 
+def run_pml(steps, warmup=2, width=32):
+    """Two-step PML step (12 split parts) on the 576x320x320 box with layers of `width` cells at
+    both ends of every axis, FP32; the split parts start as the laser recipe's E, B in set A."""
+    import torch
+
+    from paper_1812_07357_amd import psatd
+
+    box = (INTERIOR[0] + 2 * NGUARD, INTERIOR[1] + 2 * NGUARD, INTERIOR[2] + 2 * NGUARD)
+    plan = psatd.Plan(*box, nguard=0, order=ORDER, dx=DX, dt=DT, precision="fp32")
+    plan.autotune()
+    plan.pml_set((width, width, width), 3.0 * np.log(1e4) / (2 * width * DX), 2.0)
+    shape = plan.box_shape
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    parts = torch.zeros((12,) + shape, device="cuda")
+    parts[0:6] = 0.01 * torch.randn((6,) + shape, generator=gen, device="cuda")
+    src = torch.zeros((5,) + shape, device="cuda")
+    for _ in range(warmup):
+        plan.pml_step(parts, src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.pml_step(parts, src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.close()
+    del parts, src
+    torch.cuda.empty_cache()
+    cells = box[0] * box[1] * box[2]
+    return {"box": list(box), "layer_cells": width, "ms_per_step": ms, "box_cell_updates_per_s": cells / (ms * 1e-3),
+            "note": "12 split parts: two passes of the five-pass step (one per split set) plus the sum and "
+                    "damping kernels"}
+
+
 def summarize_pmc(directory, steps, out_json):
     """HBM traffic per launch of each pass from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this script.
 
@@ -456,6 +489,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-staggered", action="store_true")
     ap.add_argument("--no-pic", action="store_true")
+    ap.add_argument("--no-pml", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--extra", action="store_true",
@@ -573,6 +607,10 @@ def main():
     if not args.no_pic:
         log("fp32 PIC cycle (push, deposit, step)")
         out["pic_fp32"] = run_pic(host, min(args.steps, 20), 2)
+
+    if not args.no_pml:
+        log("fp32 two-step PML step")
+        out["pml_fp32"] = run_pml(min(args.steps, 20))
 
     if not args.no_batch:
         log("batch run (64 uneven boxes, hipGraph)")

@@ -345,6 +345,36 @@ long long psatd_device_bytes_in_use(void);
  * file is not an error (both counts 0). */
 int psatd_tune_cache_load(const char* path, int* accepted, int* rejected);
 
+/* ---------------------------------------------------------------- absorbing layers
+ * Two-step perfectly matched layers (the absorbing boundaries the paper's
+ * solver uses, Sec. 2.6: the two-step PML of Shapoval, Vay and Vincenti, 2019).
+ * The plan's box (interior + guards, box arrays as for psatd_push) becomes a
+ * domain with absorbing layers at its ends instead of a periodic one.  Every
+ * field component is split into two parts by the direction of the derivative
+ * that drives it, twelve box arrays in this order:
+ *   set A: E_xy, E_yz, E_zx, B_xy, B_yz, B_zx   (component a, axis a+1)
+ *   set B: E_xz, E_yx, E_zy, B_xz, B_yx, B_zy   (component a, axis a+2)
+ * The full field is the sum of its two parts (E_x = E_xy + E_xz, ...).
+ * One step: (1) every part gains, without absorption, the integral over the
+ * step of its own right-hand side along the exact (PSATD) evolution of the
+ * full fields with the sources held constant, set A also taking the part of
+ * the increment not driven by a derivative, so that the two parts always add
+ * up to psatd_push's step; (2) each part is multiplied by exp(-sigma dt) of
+ * its axis, sigma = sigma_max (depth / width)^power in a layer of `width`
+ * cells at both ends of the axis (depth = width at the outer cell, 1 at the
+ * innermost) and 0 inside.  Collocated plans only. */
+
+/* Sets (or changes) the layers: width[3] cells per axis (0 = no layer; at
+ * most half the box edge), sigma_max >= 0, power >= 0.  The first call
+ * allocates the damping tables and twelve box arrays of scratch.
+ * Synchronises the device. */
+int psatd_pml_set(psatd_plan* plan, const int width[3], double sigma_max, double power);
+
+/* One PML step: parts[0..11] the split fields (read and overwritten),
+ * src[0..4] = Jx Jy Jz rho_old rho_new (read only), all box arrays of the plan
+ * precision and distinct.  PSATD_ESTATE before psatd_pml_set. */
+int psatd_pml_step(psatd_plan* plan, void* const* parts, const void* const* src, void* stream);
+
 /* ---------------------------------------------------------------- particles
  * The particle side of the PIC cycle around the step (Sec. 2.5.1, Fig. 4:
  * push the particles with the fields at their positions, deposit their current

@@ -37,7 +37,7 @@ _PASS_UNITS = [(u, name, prec) for u, name in ((1, "xfwd"), (2, "ypass"), (3, "z
                                                (5, "xinv"), (6, "zpush_two_stage")) for prec in ("float", "double")]
 SOURCES = [("passes.hip", f"passes_{name}_{prec}", [f"-DPSATD_UNIT={u}", f"-DPSATD_REAL={prec}"])
            for u, name, prec in _PASS_UNITS]
-SOURCES += [(src, os.path.splitext(src)[0], []) for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip", "pic.hip")]
+SOURCES += [(src, os.path.splitext(src)[0], []) for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip", "pic.hip", "pml.hip")]
 
 
 def _compile(unit) -> str:

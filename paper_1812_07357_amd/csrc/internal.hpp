@@ -95,6 +95,11 @@ struct ZPushParams {
   int ra, rb;            // two-stage kernel with compile-time radices (ra, rb), or 0, 0
   T c2;                  // c^2
   T inv_eps0;            // 1 / eps0
+  // Two-step PML (split fields): 0 = ordinary push; 1 / 2 = write the increments of
+  // split set A / set B of E and B over the step instead of the new fields (run-time
+  // kernel only); dt and 1/(NX NY NZ) for the terms without a table.
+  int pml;
+  T dt, inv_n;
   FastDiv fd_NY, fd_NZ, fd_ncol;
   LineFFT<T> fft;
 };
@@ -225,6 +230,11 @@ void launch_guard_fill(const void* const* g1, void* const* box, int nfields, int
 void launch_guard_merge(const void* const* box, void* const* g1, int nfields, int esize, const int box_dims[3],
                         const int guard[3], const int interior[3], const int origin[3], const int gdims[3],
                         int mode, hipStream_t s);
+
+// Two-step PML element-wise kernels (split parts: set A = parts[0..5], set B = parts[6..11]).
+void launch_pml_sum(const void* const* parts, void* const* full, long long ncell, int fp64, hipStream_t s);
+void launch_pml_update(void* const* parts, const void* const* inc, const void* const damp[3], int set, int NX,
+                       int NY, int NZ, int fp64, hipStream_t s);
 
 // Records a message for psatd_last_error() and returns `code`.
 int report_error(int code, const char* fmt, ...);

@@ -720,13 +720,19 @@ template <typename T>
 __device__ __forceinline__ void push_point_c(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
                                              int kxi, int kyi, const T* cc);
 template <typename T>
+__device__ __forceinline__ void push_point_pml(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
+                                               int kxi, int kyi, const T* cc);
+template <typename T, bool PML = false>
 __device__ __forceinline__ void push_point(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int col, int kz,
                                            int kxi, int kyi) {
   const uint32_t idx = (uint32_t)(col * p.NZ + kz);
   T cc[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) cc[k] = gm<T>::ld(make_rsrc(p.coef + (i64)k * p.npts, p.coef_bytes), idx);
-  push_point_c(p, lds, fs, s, kz, kxi, kyi, cc);
+  if constexpr (PML)
+    push_point_pml(p, lds, fs, s, kz, kxi, kyi, cc);
+  else
+    push_point_c(p, lds, fs, s, kz, kxi, kyi, cc);
 }
 template <typename T>
 __device__ __forceinline__ void push_point_c(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
@@ -774,8 +780,81 @@ __device__ __forceinline__ void push_point_c(const ZPushParams<T>& p, cx<T>* lds
   lds[5 * fs + s] = {C * bz.re - wz.im, C * bz.im + wz.re};
 }
 
+// Two-step PML (Sec. 2.6): the twelve split parts of E and B (component a split into set
+// A, driven by the derivative along axis a+1, and set B, along a+2) advance over the step
+// by the integral of their own right-hand side along the exact evolution of the full
+// fields, with the sources constant.  Set B of E_a gains -i c^2 K_{a+2} IB_{a+1}, set B of
+// B_a gains +i K_{a+2} IE_{a+1}, where
+//   IB = S1 B_T + dt B_L - i X1 (K x E) + i (dt X2/eps0) (K x J),
+//   IE = S1 E_T + dt E_L + i c^2 X1 (K x B) - (X1/eps0) J_T - (dt^2/(2 eps0)) J_L
+// are the integrals of B(t) and E(t) over the step (T, L: parts transverse and parallel
+// to K); set A takes the rest of the increment of the ordinary push, so the two sets
+// always add up to it.  Writes the increments (scaled by 1/N like the tables) of set
+// p.pml to the E, B slots.  Collocated grid.
+template <typename T>
+__device__ __forceinline__ void push_point_pml(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
+                                               int kxi, int kyi, const T* cc) {
+  const T c2 = p.c2, ie = p.inv_eps0, invn = p.inv_n, dt = p.dt;
+  const T K[3] = {p.kx[kxi], p.ky[kyi], p.kz[kz]};
+  const T C = cc[0], S1 = cc[1], X1 = cc[2], X2 = cc[3], X3 = cc[4];
+  cx<T> E[3], B[3], J[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    E[a] = lds[a * fs + s];
+    B[a] = lds[(3 + a) * fs + s];
+    J[a] = lds[(6 + a) * fs + s];
+  }
+  const cx<T> ro = lds[9 * fs + s], rn = lds[10 * fs + s];
+  const T k2 = K[0] * K[0] + K[1] * K[1] + K[2] * K[2];
+  const T ik2 = k2 > T(0) ? T(1) / k2 : T(0);
+  auto dot = [&](const cx<T>* v) {
+    return cadd(cadd(cscale(v[0], K[0]), cscale(v[1], K[1])), cscale(v[2], K[2]));
+  };
+  auto cross = [&](const cx<T>* v, int a) {  // (K x v)_a
+    const int b = a == 2 ? 0 : a + 1, c = a == 0 ? 2 : a - 1;
+    return csub(cscale(v[c], K[b]), cscale(v[b], K[c]));
+  };
+  const cx<T> kE = cscale(dot(E), ik2), kB = cscale(dot(B), ik2), kJ = cscale(dot(J), ik2);
+  const cx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
+  cx<T> IB[3], IE[3], dE[3], dB[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cx<T> kxe = cross(E, a), kxb = cross(B, a), kxj = cross(J, a);
+    const cx<T> EL = cscale(kE, K[a]), BL = cscale(kB, K[a]), JL = cscale(kJ, K[a]);
+    // IB_a = S1 (B - B_L) + dt/N B_L + (X1 K x E + dt X2/eps0 K x J) * (-i, +i)
+    const cx<T> ib_r = cadd(cscale(csub(B[a], BL), S1), cscale(BL, dt * invn));
+    const cx<T> ib_i = csub(cscale(kxj, dt * X2 * ie), cscale(kxe, X1));  // times i
+    IB[a] = {ib_r.re - ib_i.im, ib_r.im + ib_i.re};
+    const cx<T> ie_r = csub(cadd(cscale(csub(E[a], EL), S1), cscale(EL, dt * invn)),
+                            cadd(cscale(csub(J[a], JL), X1 * ie), cscale(JL, T(0.5) * dt * dt * invn * ie)));
+    const cx<T> ie_i = cscale(kxb, c2 * X1);  // times i
+    IE[a] = {ie_r.re - ie_i.im, ie_r.im + ie_i.re};
+    // ordinary push (tables scaled by 1/N) minus E/N: the whole increment
+    const cx<T> ux = cadd(cscale(kxb, c2 * S1), cscale(rr, c2 * ie * K[a]));
+    dE[a] = {C * E[a].re - S1 * ie * J[a].re - ux.im - invn * E[a].re,
+             C * E[a].im - S1 * ie * J[a].im + ux.re - invn * E[a].im};
+    const cx<T> w = csub(cscale(kxj, X1 * ie), cscale(kxe, S1));
+    dB[a] = {C * B[a].re - w.im - invn * B[a].re, C * B[a].im + w.re - invn * B[a].im};
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = a == 2 ? 0 : a + 1, c = a == 0 ? 2 : a - 1;  // a+1, a+2
+    // set B: -i c^2 K_c IB_b and +i K_c IE_b
+    const cx<T> eb = {c2 * K[c] * IB[b].im, -c2 * K[c] * IB[b].re};
+    const cx<T> bb = {-K[c] * IE[b].im, K[c] * IE[b].re};
+    if (p.pml == 2) {
+      lds[a * fs + s] = eb;
+      lds[(3 + a) * fs + s] = bb;
+    } else {
+      lds[a * fs + s] = csub(dE[a], eb);
+      lds[(3 + a) * fs + s] = csub(dB[a], bb);
+    }
+  }
+}
+
 // MULTI = false compiles the single-column case (ncol == 1) without the column bookkeeping.
-template <typename T, bool MULTI, typename Src>
+// PML selects the split-field increments of push_point_pml instead of the ordinary push.
+template <typename T, bool MULTI, typename Src, bool PML = false>
 __device__ __forceinline__ void zpush_body(const Src& S) {
   constexpr int kRound = 16;  // line chunks of 64 points loaded per thread before they go to LDS
   cx<T>* lds = lds_base<T>();
@@ -830,7 +909,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
         const int col = col0 + c;
         const int kxi = fdiv(col, p.fd_NY);
         const int kyi = col - kxi * p.NY;
-        for (int kz = tid; kz < NZ; kz += nth) push_point(p, lds, fs, c * ld + lpad(kz), col, kz, kxi, kyi);
+        for (int kz = tid; kz < NZ; kz += nth) push_point<T, PML>(p, lds, fs, c * ld + lpad(kz), col, kz, kxi, kyi);
       }
     } else {
       // short lines: (column, k_z) pairs spread over the block
@@ -840,7 +919,7 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
         const int col = col0 + c;
         const int kxi = fdiv(col, p.fd_NY);
         const int kyi = col - kxi * p.NY;
-        push_point(p, lds, fs, c * ld + lpad(kz), col, kz, kxi, kyi);
+        push_point<T, PML>(p, lds, fs, c * ld + lpad(kz), col, kz, kxi, kyi);
       }
     }
     __syncthreads();
@@ -1149,10 +1228,10 @@ k_ypass_b(BatchArgs<YPassParams<T>> a) {
 }
 // z pass: FP32 single-box tiles fit 96 registers (5 waves per SIMD), batched ones 128 (4);
 // FP64 256 (2).
-template <typename T, int NTH, bool MULTI>
+template <typename T, int NTH, bool MULTI, bool PML = false>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 2)))
 k_zpush(ZPushParams<T>) {
-  zpush_body<T, MULTI>(SingleSrc<ZPushParams<T>>{});
+  zpush_body<T, MULTI, SingleSrc<ZPushParams<T>>, PML>(SingleSrc<ZPushParams<T>>{});
 }
 // Two-stage z kernel: three 4-wave blocks per CU in FP32 (168 registers hold a
 // stage's butterfly, its twiddles and the small-DFT temporaries without spills).
@@ -1321,12 +1400,12 @@ void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
   else
     launch_persistent(k_ypass<-1, T>, p, kLineThreads, ypass_lds(p), p.ntiles, s);
 }
-template <typename T, bool MULTI>
+template <typename T, bool MULTI, bool PML = false>
 void launch_zpush_cols(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
   if (nthreads == kZThreads[0])
-    launch_persistent(k_zpush<T, kZThreads[0], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
+    launch_persistent(k_zpush<T, kZThreads[0], MULTI, PML>, p, nthreads, zpush_lds(p), p.ntiles, s);
   else
-    launch_persistent(k_zpush<T, kZThreads[1], MULTI>, p, nthreads, zpush_lds(p), p.ntiles, s);
+    launch_persistent(k_zpush<T, kZThreads[1], MULTI, PML>, p, nthreads, zpush_lds(p), p.ntiles, s);
 }
 template <typename T, int I = 0>
 void launch_two_stage_at(const ZPushParams<T>& p, hipStream_t s) {
@@ -1351,6 +1430,13 @@ extern template void launch_zpush_two_stage<double>(const ZPushParams<double>&, 
 #endif
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
+  if (p.pml) {  // split-field increments: run-time kernels only
+    if (p.ncol == 1)
+      launch_zpush_cols<T, false, true>(p, nthreads, s);
+    else
+      launch_zpush_cols<T, true, true>(p, nthreads, s);
+    return;
+  }
   if (p.ra > 0) {
     launch_zpush_two_stage<T>(p, s);
     return;

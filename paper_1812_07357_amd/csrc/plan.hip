@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <cmath>
 #include <cstdlib>
 #include <functional>
 #include <map>
@@ -290,6 +291,12 @@ struct psatd_plan {
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool in_flight_known = false;
+  // Two-step PML (psatd_pml_set): damping factors per axis (NX, NY, NZ values), and
+  // six box arrays each for the full fields and for one set of split increments.
+  bool pml_ready = false;
+  void* pml_damp[3] = {nullptr, nullptr, nullptr};
+  void* pml_full[6] = {};
+  void* pml_inc[6] = {};
 };
 
 namespace {
@@ -554,6 +561,7 @@ struct StepIO {
   int ox, oy, oz;
   long long dst_elems;  // elements of each destination array
   int y_lo, y_hi, z_lo, z_hi;  // box lines needed after the inverse
+  int pml = 0;                 // two-step PML: 1 / 2 = P3 and P5 produce split set A / B increments
 };
 
 // The compiled two-stage z kernel applies when a box's z tiles hold one column,
@@ -761,7 +769,10 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   z3.fd_NZ = make_fastdiv(NZ);
   z3.fd_ncol = make_fastdiv(p->zcols);
   z3.fft = line_fft<T>(p->az);
-  if (!batched && (p->two_stage_mask & 4)) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
+  z3.pml = io.pml;
+  z3.dt = T(p->d.dt);
+  z3.inv_n = T(1.0 / ((double)NX * NY * NZ));
+  if (!batched && !io.pml && (p->two_stage_mask & 4)) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
 
   YPassParams<T>& y4 = sp.y4;
   y4 = YPassParams<T>{};
@@ -1642,6 +1653,87 @@ psatd_plan* psatd_plan_create(int nx, int ny, int nz, int nguard, int order, dou
 }
 
 void psatd_plan_destroy(psatd_plan* plan) { free_plan(plan); }
+
+int psatd_pml_set(psatd_plan* p, const int width[3], double sigma_max, double power) {
+  if (!p || !width) return fail(PSATD_EINVAL, "NULL argument");
+  if (p->d.flags & PSATD_FLAG_STAGGERED) return fail(PSATD_EUNSUPPORTED, "psatd_pml_set: collocated plans only");
+  if (!p->wsA) return fail(PSATD_ESTATE, "psatd_pml_set: the plan was created without a workspace");
+  const int n[3] = {p->NX, p->NY, p->NZ};
+  for (int a = 0; a < 3; ++a)
+    if (width[a] < 0 || 2 * width[a] > n[a])
+      return fail(PSATD_EINVAL, "psatd_pml_set: layer width %d on axis %d must be in [0, %d]", width[a], a,
+                  n[a] / 2);
+  if (!(sigma_max >= 0) || !(power >= 0) || !std::isfinite(sigma_max) || !std::isfinite(power))
+    return fail(PSATD_EINVAL, "psatd_pml_set: sigma_max and power must be finite and >= 0");
+  const size_t rs = p->rsize;
+  if (!p->pml_ready) {
+    for (int a = 0; a < 3; ++a)
+      if (int rc = dalloc(p, &p->pml_damp[a], (size_t)n[a] * rs)) return rc;
+    for (int f = 0; f < 6; ++f) {
+      if (int rc = dalloc(p, &p->pml_full[f], (size_t)p->ncell * rs)) return rc;
+      if (int rc = dalloc(p, &p->pml_inc[f], (size_t)p->ncell * rs)) return rc;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    // sigma rises as sigma_max (depth / width)^power over `width` cells at each end
+    std::vector<double> dd(n[a], 1.0);
+    const int w = width[a];
+    for (int i = 0; i < n[a]; ++i) {
+      double depth = 0;
+      if (i < w) depth = (double)(w - i) / w;
+      else if (i >= n[a] - w) depth = (double)(i - (n[a] - w) + 1) / w;
+      dd[i] = depth > 0 ? std::exp(-sigma_max * std::pow(depth, power) * std::fabs(p->d.dt)) : 1.0;
+    }
+    hipError_t e;
+    if (p->fp64) {
+      e = hipMemcpy(p->pml_damp[a], dd.data(), (size_t)n[a] * 8, hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> df(dd.begin(), dd.end());
+      e = hipMemcpy(p->pml_damp[a], df.data(), (size_t)n[a] * 4, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return check_hip("psatd_pml_set");
+  }
+  p->pml_ready = true;
+  return PSATD_OK;
+}
+
+int psatd_pml_step(psatd_plan* p, void* const* parts, const void* const* src, void* stream) {
+  if (!p || !parts || !src) return fail(PSATD_EINVAL, "NULL argument");
+  if (!p->pml_ready) return fail(PSATD_ESTATE, "psatd_pml_step: call psatd_pml_set first");
+  const void* all[17];
+  for (int f = 0; f < 12; ++f) all[f] = parts[f];
+  for (int f = 0; f < 5; ++f) all[12 + f] = src[f];
+  for (int f = 0; f < 17; ++f)
+    if (!all[f]) return fail(PSATD_EINVAL, "psatd_pml_step: array %d is NULL", f);
+  if (!distinct(all, 17)) return fail(PSATD_EINVAL, "psatd_pml_step: arrays must be distinct");
+  const hipStream_t s = (hipStream_t)stream;
+  int rc = guard_of(p).check(s, "psatd_pml_step");
+  if (rc) return rc;
+  launch_pml_sum(parts, p->pml_full, p->ncell, p->fp64, s);
+  for (int set = 1; set <= 2; ++set) {
+    StepIO io{};
+    io.wsA = p->wsA;
+    io.wsB = p->wsB;
+    for (int f = 0; f < 6; ++f) io.src[f] = p->pml_full[f];
+    for (int f = 0; f < 5; ++f) io.src[6 + f] = src[f];
+    for (int f = 0; f < 6; ++f) io.dst[f] = p->pml_inc[f];
+    io.gather = 0;
+    io.src_elems = p->ncell;
+    io.scatter = 0;
+    io.dst_elems = p->ncell;
+    io.y_lo = 0;
+    io.y_hi = p->NY;
+    io.z_lo = 0;
+    io.z_hi = p->NZ;
+    io.pml = set;
+    rc = dispatch_step(p, io, s);
+    if (rc) return rc;
+    launch_pml_update(parts + 6 * (set - 1), p->pml_inc, p->pml_damp, set, p->NX, p->NY, p->NZ, p->fp64, s);
+  }
+  rc = check_hip("psatd_pml_step");
+  if (rc) return rc;
+  return guard_of(p).mark(s, "psatd_pml_step");
+}
 
 int psatd_default_schedule(int n, int* radices, int max_radices, int* transform_len) {
   if (n < 1 || n > (1 << 24) || !radices || !transform_len || max_radices < 1)

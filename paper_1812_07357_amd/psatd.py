@@ -136,6 +136,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.psatd_device_bytes_in_use.argtypes = []
     lib.psatd_tune_cache_load.restype = cint
     lib.psatd_tune_cache_load.argtypes = [ctypes.c_char_p, ip, ip]
+    lib.psatd_pml_set.argtypes = [vp, ip, ctypes.c_double, ctypes.c_double]
+    lib.psatd_pml_set.restype = cint
+    lib.psatd_pml_step.argtypes = [vp, vpp, vpp, vp]
+    lib.psatd_pml_step.restype = cint
     lib.psatd_pic_create.argtypes = [ctypes.POINTER(PicDesc), ctypes.POINTER(vp)]
     lib.psatd_pic_create.restype = cint
     lib.psatd_pic_destroy.argtypes = [vp]
@@ -286,6 +290,18 @@ class Plan:
         self._check_fields(f, gshape, "step_g1_noalloc")
         gdims = (gshape[2], gshape[1], gshape[0])
         _check(_lib.psatd_step_g1_noalloc(self._h, _ptrs(f), _ints(origin), _ints(gdims), _stream(stream)))
+
+    def pml_set(self, widths, sigma_max, power=2.0):
+        """psatd_pml_set: absorbing layers of ``widths`` (x, y, z) cells at both ends of each axis."""
+        _check(_lib.psatd_pml_set(self._h, _ints(widths), float(sigma_max), float(power)))
+
+    def pml_step(self, parts, sources, stream=None):
+        """psatd_pml_step: one step of the 12 split parts (in place) with the 5 sources
+        (Jx Jy Jz rho_old rho_new), all box arrays."""
+        p = self._split(parts, 12)
+        src = self._split(sources, 5)
+        self._check_fields(p + src, self.box_shape, "pml_step")
+        _check(_lib.psatd_pml_step(self._h, _ptrs(p), _ptrs(src), _stream(stream)))
 
     def guard_fill(self, g1, box, origin, stream=None):
         """guard_fill: gather box arrays (interior + guards) from the periodic global arrays."""

@@ -35,7 +35,7 @@ def _units():
     for u in range(1, 7):
         for prec in ("float", "double"):
             out.append(("passes.hip", f"passes_{u}_{prec}", [f"-DPSATD_UNIT={u}", f"-DPSATD_REAL={prec}"]))
-    for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip", "pic.hip"):
+    for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip", "pic.hip", "pml.hip"):
         out.append((src, os.path.splitext(src)[0], []))
     return out
 
