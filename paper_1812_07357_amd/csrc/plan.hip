@@ -1331,12 +1331,18 @@ int autotune_plan(psatd_plan* p, hipStream_t s) {
           p->two_stage_mask = (p->two_stage_mask & ~bit) | (hit->second.kern & bit);
           continue;
         }
-        p->two_stage_mask |= bit;
-        const float t2 = time_pass<T>(p, pass, 3, s);
-        p->two_stage_mask &= ~bit;
-        const float t1 = time_pass<T>(p, pass, 3, s);
+        // alternate the two kernels and keep each one's best time; leave the default
+        // kernel of the pass only for a gain above 2 % (run-to-run noise is about 1 %)
+        float t2 = 1e30f, t1 = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          p->two_stage_mask |= bit;
+          t2 = std::min(t2, time_pass<T>(p, pass, 3, s));
+          p->two_stage_mask &= ~bit;
+          t1 = std::min(t1, time_pass<T>(p, pass, 3, s));
+        }
         if (hipGetLastError() != hipSuccess) continue;
-        if (t2 < t1) p->two_stage_mask |= bit;
+        const bool two_stage_default = (kTwoStageDefault & bit) != 0;
+        if (two_stage_default ? !(t1 < 0.98f * t2) : (t2 < 0.98f * t1)) p->two_stage_mask |= bit;
       }
       best_e.kern = p->two_stage_mask & ((a == 0) ? (1 | 16) : (a == 1) ? (2 | 8) : 4);
     }
