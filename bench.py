@@ -367,8 +367,8 @@ def run_pml(steps, warmup=2, width=32):
     torch.cuda.empty_cache()
     cells = box[0] * box[1] * box[2]
     return {"box": list(box), "layer_cells": width, "ms_per_step": ms, "box_cell_updates_per_s": cells / (ms * 1e-3),
-            "note": "12 split parts: two passes of the five-pass step (one per split set) plus the sum and "
-                    "damping kernels"}
+            "note": "12 split parts: forward x, y and z passes once (the z pass writes both split sets), "
+                    "inverse y and x passes per set, plus the sum and damping kernels"}
 
 
 def summarize_pmc(directory, steps, out_json):

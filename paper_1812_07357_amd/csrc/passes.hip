@@ -789,8 +789,9 @@ __device__ __forceinline__ void push_point_c(const ZPushParams<T>& p, cx<T>* lds
 //   IE = S1 E_T + dt E_L + i c^2 X1 (K x B) - (X1/eps0) J_T - (dt^2/(2 eps0)) J_L
 // are the integrals of B(t) and E(t) over the step (T, L: parts transverse and parallel
 // to K); set A takes the rest of the increment of the ordinary push, so the two sets
-// always add up to it.  Writes the increments (scaled by 1/N like the tables) of set
-// p.pml to the E, B slots.  Collocated grid.
+// always add up to it.  Writes the increments (scaled by 1/N like the tables) of set A
+// to slots 0..5 and of set B to slots 6..11 (in the split-part order E_xz E_yx E_zy
+// B_xz B_yx B_zy); the sources in slots 6..10 are read first.  Collocated grid.
 template <typename T>
 __device__ __forceinline__ void push_point_pml(const ZPushParams<T>& p, cx<T>* lds, int fs, int s, int kz,
                                                int kxi, int kyi, const T* cc) {
@@ -842,18 +843,16 @@ __device__ __forceinline__ void push_point_pml(const ZPushParams<T>& p, cx<T>* l
     // set B: -i c^2 K_c IB_b and +i K_c IE_b
     const cx<T> eb = {c2 * K[c] * IB[b].im, -c2 * K[c] * IB[b].re};
     const cx<T> bb = {-K[c] * IE[b].im, K[c] * IE[b].re};
-    if (p.pml == 2) {
-      lds[a * fs + s] = eb;
-      lds[(3 + a) * fs + s] = bb;
-    } else {
-      lds[a * fs + s] = csub(dE[a], eb);
-      lds[(3 + a) * fs + s] = csub(dB[a], bb);
-    }
+    lds[a * fs + s] = csub(dE[a], eb);
+    lds[(3 + a) * fs + s] = csub(dB[a], bb);
+    lds[(6 + a) * fs + s] = eb;
+    lds[(9 + a) * fs + s] = bb;
   }
 }
 
 // MULTI = false compiles the single-column case (ncol == 1) without the column bookkeeping.
-// PML selects the split-field increments of push_point_pml instead of the ordinary push.
+// PML selects the split-field increments of push_point_pml instead of the ordinary push:
+// twelve output lines per column (both split sets) instead of six.
 template <typename T, bool MULTI, typename Src, bool PML = false>
 __device__ __forceinline__ void zpush_body(const Src& S) {
   constexpr int kRound = 16;  // line chunks of 64 points loaded per thread before they go to LDS
@@ -923,13 +922,14 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
       }
     }
     __syncthreads();
-    if (p.zgroup >= 6 * ncol)
-      lds_line_fft<1, T>(lds, ld, 6 * ncol, p.fft);
+    constexpr int kOut = PML ? 12 : 6;  // output lines per column
+    if (p.zgroup >= kOut * ncol)
+      lds_line_fft<1, T>(lds, ld, kOut * ncol, p.fft);
     else
-      for (int l0 = 0; l0 < 6 * ncol; l0 += p.zgroup)
-        lds_line_fft<1, T>(lds + l0 * ld, ld, min(p.zgroup, 6 * ncol - l0), p.fft);
+      for (int l0 = 0; l0 < kOut * ncol; l0 += p.zgroup)
+        lds_line_fft<1, T>(lds + l0 * ld, ld, min(p.zgroup, kOut * ncol - l0), p.fft);
 
-    for (int l = wave; l < 6 * ncol; l += nwaves) {
+    for (int l = wave; l < kOut * ncol; l += nwaves) {
       const int f = MULTI ? fdiv(l, p.fd_ncol) : l, c = MULTI ? l - f * ncol : 0;
       if (MULTI && c >= nct) continue;
       const rsrc_t rb = make_rsrc(p.b + (i64)f * p.npts, p.field_bytes);
@@ -1331,7 +1331,7 @@ size_t ypass_lds(const YPassParams<T>& p) {
 }
 template <typename T>
 size_t zpush_lds(const ZPushParams<T>& p) {
-  return (size_t)11 * p.ncol * fft_slots(p.fft.sch.n) * cx_bytes<T>();
+  return (size_t)(p.pml ? 12 : 11) * p.ncol * fft_slots(p.fft.sch.n) * cx_bytes<T>();
 }
 template <typename T>
 size_t xinv_lds(const XInvParams<T>& p) {

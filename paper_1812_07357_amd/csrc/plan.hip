@@ -294,6 +294,7 @@ struct psatd_plan {
   // Two-step PML (psatd_pml_set): damping factors per axis (NX, NY, NZ values), and
   // six box arrays each for the full fields and for one set of split increments.
   bool pml_ready = false;
+  void* pml_wsB = nullptr;  // layout B with 12 fields (P3 writes both split sets)
   void* pml_damp[3] = {nullptr, nullptr, nullptr};
   void* pml_full[6] = {};
   void* pml_inc[6] = {};
@@ -561,7 +562,7 @@ struct StepIO {
   int ox, oy, oz;
   long long dst_elems;  // elements of each destination array
   int y_lo, y_hi, z_lo, z_hi;  // box lines needed after the inverse
-  int pml = 0;                 // two-step PML: 1 / 2 = P3 and P5 produce split set A / B increments
+  int pml = 0;                 // two-step PML: P3 writes the twelve split increments (wsB holds 12 fields)
 };
 
 // The compiled two-stage z kernel applies when a box's z tiles hold one column,
@@ -772,6 +773,14 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
   z3.pml = io.pml;
   z3.dt = T(p->d.dt);
   z3.inv_n = T(1.0 / ((double)NX * NY * NZ));
+  if (io.pml) {  // twelve lines per column in LDS: fewer columns per tile if needed
+    int nc = p->zcols;
+    while (nc > 1 && (size_t)12 * nc * lds_line(p->az.sch.n) * sizeof(cx<T>) > z_lds(nc)) --nc;
+    z3.ncol = nc;
+    z3.ntiles = (NXH * NY + nc - 1) / nc;
+    z3.fd_ncol = make_fastdiv(nc);
+    z3.zgroup = z_group(p->az.sch, p->zthreads, emax<T>::v, sizeof(cx<T>), 12 * nc);
+  }
   if (!batched && !io.pml && (p->two_stage_mask & 4)) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
 
   YPassParams<T>& y4 = sp.y4;
@@ -881,6 +890,26 @@ int run_step(psatd_plan* p, const StepIO& io, hipStream_t s, bool allow_timing =
   launch_xinv<T>(sp.x5, s);
   mk.mark(5);
   return check_hip("step kernels");
+}
+
+// Two-step PML step on the split parts: forward passes and the z pass once (the z pass
+// writes both split sets' increments, 12 fields of layout B), then per set the inverse y
+// and x passes into the increment arrays and the damped update of that set's parts.
+template <typename T>
+int run_pml(psatd_plan* p, const StepIO& io, void* const* parts, hipStream_t s) {
+  StepParams<T> sp;
+  build_step<T>(p, io, sp);
+  launch_xfwd<T>(sp.x1, s);
+  launch_ypass<T>(sp.y2, 0, s);
+  launch_zpush<T>(sp.z3, p->zthreads, s);
+  for (int set = 0; set < 2; ++set) {
+    YPassParams<T> y4 = sp.y4;
+    y4.in = (const cx<T>*)io.wsB + (i64)6 * set * p->npts;
+    launch_ypass<T>(y4, 1, s);
+    launch_xinv<T>(sp.x5, s);
+    launch_pml_update(parts + 6 * set, p->pml_inc, p->pml_damp, set + 1, p->NX, p->NY, p->NZ, p->fp64, s);
+  }
+  return check_hip("psatd_pml_step");
 }
 
 // Streams: an object (plan or batch) owns its workspace, so a step may start on
@@ -1672,7 +1701,10 @@ int psatd_pml_set(psatd_plan* p, const int width[3], double sigma_max, double po
   if (!(sigma_max >= 0) || !(power >= 0) || !std::isfinite(sigma_max) || !std::isfinite(power))
     return fail(PSATD_EINVAL, "psatd_pml_set: sigma_max and power must be finite and >= 0");
   const size_t rs = p->rsize;
+  if ((size_t)12 * lds_line(p->az.sch.n) * 2 * rs > lds_limit())
+    return fail(PSATD_EUNSUPPORTED, "psatd_pml_set: twelve z lines of %d points do not fit the LDS", p->az.sch.n);
   if (!p->pml_ready) {
+    if (int rc = dalloc(p, &p->pml_wsB, (size_t)12 * p->npts * 2 * rs)) return rc;
     for (int a = 0; a < 3; ++a)
       if (int rc = dalloc(p, &p->pml_damp[a], (size_t)n[a] * rs)) return rc;
     for (int f = 0; f < 6; ++f) {
@@ -1716,27 +1748,22 @@ int psatd_pml_step(psatd_plan* p, void* const* parts, const void* const* src, vo
   int rc = guard_of(p).check(s, "psatd_pml_step");
   if (rc) return rc;
   launch_pml_sum(parts, p->pml_full, p->ncell, p->fp64, s);
-  for (int set = 1; set <= 2; ++set) {
-    StepIO io{};
-    io.wsA = p->wsA;
-    io.wsB = p->wsB;
-    for (int f = 0; f < 6; ++f) io.src[f] = p->pml_full[f];
-    for (int f = 0; f < 5; ++f) io.src[6 + f] = src[f];
-    for (int f = 0; f < 6; ++f) io.dst[f] = p->pml_inc[f];
-    io.gather = 0;
-    io.src_elems = p->ncell;
-    io.scatter = 0;
-    io.dst_elems = p->ncell;
-    io.y_lo = 0;
-    io.y_hi = p->NY;
-    io.z_lo = 0;
-    io.z_hi = p->NZ;
-    io.pml = set;
-    rc = dispatch_step(p, io, s);
-    if (rc) return rc;
-    launch_pml_update(parts + 6 * (set - 1), p->pml_inc, p->pml_damp, set, p->NX, p->NY, p->NZ, p->fp64, s);
-  }
-  rc = check_hip("psatd_pml_step");
+  StepIO io{};
+  io.wsA = p->wsA;
+  io.wsB = p->pml_wsB;
+  for (int f = 0; f < 6; ++f) io.src[f] = p->pml_full[f];
+  for (int f = 0; f < 5; ++f) io.src[6 + f] = src[f];
+  for (int f = 0; f < 6; ++f) io.dst[f] = p->pml_inc[f];
+  io.gather = 0;
+  io.src_elems = p->ncell;
+  io.scatter = 0;
+  io.dst_elems = p->ncell;
+  io.y_lo = 0;
+  io.y_hi = p->NY;
+  io.z_lo = 0;
+  io.z_hi = p->NZ;
+  io.pml = 1;
+  rc = p->fp64 ? run_pml<double>(p, io, parts, s) : run_pml<float>(p, io, parts, s);
   if (rc) return rc;
   return guard_of(p).mark(s, "psatd_pml_step");
 }
