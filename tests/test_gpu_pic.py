@@ -149,24 +149,27 @@ def test_deposit_of_no_particles_clears_the_sources(lib):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_pic_cycle_matches_oracle(lib, precision):
+@pytest.mark.parametrize("staggered", [False, True])
+def test_pic_cycle_matches_oracle(lib, precision, staggered):
     """Three PIC cycles: gather + push, deposit, local PSATD step on four FFT boxes (D2)
-    whose edges differ from the D1 tiles, against the same cycle in the oracle."""
+    whose edges differ from the D1 tiles, against the same cycle in the oracle; on the
+    collocated and on the staggered (Yee) grid."""
     import torch
 
     gdims, d, dt, c = (32, 24, 20), (1.0, 1.0, 1.0), 0.45, 1.0
     L = _lengths(gdims, d)
     gshape = (gdims[2], gdims[1], gdims[0])
-    boxes = [dict(origin=(0, 0, 0), interior=(18, 24, 20), nguard=4, order=8),
-             dict(origin=(18, 0, 0), interior=(14, 11, 20), nguard=(4, 5, 3), order=8),
-             dict(origin=(18, 11, 0), interior=(14, 13, 9), nguard=6, order=16),
-             dict(origin=(18, 11, 9), interior=(14, 13, 11), nguard=3, order=0)]
+    boxes = [dict(origin=(0, 0, 0), interior=(18, 24, 20), nguard=4, order=8, staggered=staggered),
+             dict(origin=(18, 0, 0), interior=(14, 11, 20), nguard=(4, 5, 3), order=8, staggered=staggered),
+             dict(origin=(18, 11, 0), interior=(14, 13, 9), nguard=6, order=16, staggered=staggered),
+             dict(origin=(18, 11, 9), interior=(14, 13, 11), nguard=3, order=0, staggered=staggered)]
     x, u = synth.plasma_particles(synth.rng_for(165, 0), 4000, L, 0.3)
     x, u = _as_inputs(x, u, precision, L)
     q, qm = -0.05, -1.0
     f = 0.05 * synth.random_fields(synth.rng_for(166, 0), gshape, 11, 1.0)
     f[6:] = 0.0
-    p = lib.Pic(gdims, dx=d, dt=dt, c=c, q=q, q_over_m=qm, max_particles=len(x), tile=8, precision=precision)
+    p = lib.Pic(gdims, dx=d, dt=dt, c=c, q=q, q_over_m=qm, max_particles=len(x), tile=8, precision=precision,
+                staggered=staggered)
     batch = lib.Batch(boxes, gdims, dx=d, dt=dt, precision=precision)
     g = _gpu(f, p)
     f = g.double().cpu().numpy()
@@ -176,8 +179,8 @@ def test_pic_cycle_matches_oracle(lib, precision):
         p.push(g, xg, ug, xo)
         p.deposit(g, xo, xg, ug)
         batch.step(g)
-        xn, u = pic.push(x, u, f, gshape, d, qm, dt, c)
-        J, r0, r1 = pic.sources(x, xn, u, q, gshape, d, dt, c)
+        xn, u = pic.push(x, u, f, gshape, d, qm, dt, c, staggered=staggered)
+        J, r0, r1 = pic.sources(x, xn, u, q, gshape, d, dt, c, staggered=staggered)
         f[6:9], f[9], f[10] = J, r0, r1
         f = domain.local_step(f, boxes, d, dt, c)
         x = xn
