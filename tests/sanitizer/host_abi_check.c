@@ -146,6 +146,13 @@ int main(int argc, char** argv) {
     psatd_pic_destroy(NULL);
   }
   {
+    int w[3] = {1, 1, 1};
+    CHECK(psatd_pml_set(NULL, w, 1.0, 2.0) == PSATD_EINVAL);
+    CHECK(psatd_pml_step(NULL, NULL, NULL, NULL) == PSATD_EINVAL);
+    CHECK(psatd_pic_push(NULL, NULL, NULL, NULL, NULL, 0, NULL) == PSATD_EINVAL);
+    CHECK(psatd_pic_deposit(NULL, NULL, NULL, NULL, NULL, 0, NULL) == PSATD_EINVAL);
+  }
+  {
     const long long before = psatd_device_bytes_in_use();
     CHECK(psatd_set_device_budget(1 << 20) == PSATD_OK);
     CHECK(psatd_set_device_budget(-1) == PSATD_OK);

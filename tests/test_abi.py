@@ -234,3 +234,11 @@ def test_pic_null_arguments(lib):
     assert L.psatd_pic_push(None, None, None, None, None, 0, None) == lib.PSATD_EINVAL
     assert L.psatd_pic_deposit(None, None, None, None, None, 0, None) == lib.PSATD_EINVAL
     L.psatd_pic_destroy(None)  # NULL-safe
+
+
+def test_pml_null_arguments(lib):
+    L = lib._lib
+    w = (ctypes.c_int * 3)(1, 1, 1)
+    assert L.psatd_pml_set(None, w, 1.0, 2.0) == lib.PSATD_EINVAL
+    assert L.psatd_pml_step(None, None, None, None) == lib.PSATD_EINVAL
+
