@@ -97,8 +97,7 @@ struct ZPushParams {
   T inv_eps0;            // 1 / eps0
   // Two-step PML (split fields): 0 = ordinary push; 1 = write the increments of the
   // twelve split parts over the step (set A to fields 0..5, set B to 6..11 of b, which
-  // then holds 12 fields; run-time kernel only); dt and 1/(NX NY NZ) for the terms
-  // without a table.
+  // then holds 12 fields); dt and 1/(NX NY NZ) for the terms without a table.
   int pml;
   T dt, inv_n;
   FastDiv fd_NY, fd_NZ, fd_ncol;

@@ -954,7 +954,8 @@ __device__ __forceinline__ void zpush_body(const Src& S) {
 //     the transform at j' + RA t (natural order).
 // The forward results of the 11 lines are written to LDS in natural order for
 // the push; the 6 lines of E and B then run stage A from LDS and stage B
-// straight to global memory (interior z only).
+// straight to global memory (interior z only).  PML: the push writes the twelve
+// split-part increments (a twelfth LDS line), and all twelve lines go back.
 template <int RA, int RB>
 struct TwoStage {
   static constexpr int N = RA * RB;
@@ -962,14 +963,15 @@ struct TwoStage {
   static constexpr int LD = two_stage_slots(RA, RB);  // LDS slots per line
 };
 
-template <typename T, int RA, int RB, int NTH, typename Src>
+template <typename T, int RA, int RB, int NTH, typename Src, bool PML = false>
 __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
   using G = TwoStage<RA, RB>;
   constexpr int N = G::N, PA = G::PA, LD = G::LD;
+  constexpr int kLines = PML ? 12 : 11, kOut = PML ? 12 : 6;  // LDS lines, lines transformed back
   cx<T>* lds = lds_base<T>();
   const int tid = threadIdx.x;
   // stage B twiddles w^(t k), copied once per launch to LDS as [t - 1][k] (lanes take consecutive k)
-  Tw<T>* twl = reinterpret_cast<Tw<T>*>(lds + 11 * LD);
+  Tw<T>* twl = reinterpret_cast<Tw<T>*>(lds + kLines * LD);
   {
     int col0;
     const ZPushParams<T>& p0 = S.box(blockIdx.x, col0);
@@ -1049,18 +1051,23 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
 #pragma unroll
       for (int u = 0; u < NP; ++u) {
         const int kz = u * NTH + tid;
-        if (kz < N) push_point_c(p, lds, LD, kz, kz, kxi, kyi, cof[u]);
+        if (kz < N) {
+          if constexpr (PML)
+            push_point_pml(p, lds, LD, kz, kz, kxi, kyi, cof[u]);
+          else
+            push_point_c(p, lds, LD, kz, kz, kxi, kyi, cof[u]);
+        }
       }
     }
     __syncthreads();
-    // inverse stage A on the 6 lines of E and B, from LDS (natural order) back to rows
+    // inverse stage A on the 6 lines of E and B (PML: 12), from LDS (natural order) back to rows
     {
-      constexpr int NA = (6 * RB + NTH - 1) / NTH;
+      constexpr int NA = (kOut * RB + NTH - 1) / NTH;
       cx<T> v[NA][RA];
 #pragma unroll
       for (int u = 0; u < NA; ++u) {
         const int b = u * NTH + tid;
-        if (b < 6 * RB) {
+        if (b < kOut * RB) {
           const int f = b / RB, j = b - f * RB;
           const cx<T>* x = lds + f * LD + j;
 #pragma unroll
@@ -1072,7 +1079,7 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
 #pragma unroll
       for (int u = 0; u < NA; ++u) {
         const int b = u * NTH + tid;
-        if (b < 6 * RB) {
+        if (b < kOut * RB) {
           const int f = b / RB, j = b - f * RB;
           cx<T>* y = lds + f * LD + j * PA;
 #pragma unroll
@@ -1083,9 +1090,9 @@ __device__ __forceinline__ void zpush_two_stage_body(const Src& S) {
     __syncthreads();
     // inverse stage B: rows -> twiddles -> DFT -> global (interior z only)
 #pragma unroll
-    for (int b0 = 0; b0 < 6 * RA; b0 += NTH) {
+    for (int b0 = 0; b0 < kOut * RA; b0 += NTH) {
       const int b = b0 + tid;
-      if (b0 + NTH <= 6 * RA || b < 6 * RA) {
+      if (b0 + NTH <= kOut * RA || b < kOut * RA) {
         const int f = b / RA, k = b - f * RA;
         const cx<T>* y = lds + f * LD + k;
         cx<T> v[RB];
@@ -1235,10 +1242,10 @@ k_zpush(ZPushParams<T>) {
 }
 // Two-stage z kernel: three 4-wave blocks per CU in FP32 (168 registers hold a
 // stage's butterfly, its twiddles and the small-DFT temporaries without spills).
-template <typename T, int RA, int RB>
+template <typename T, int RA, int RB, bool PML = false>
 __global__ void __launch_bounds__(kZTwoStageThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
 k_zpush2(ZPushParams<T>) {
-  zpush_two_stage_body<T, RA, RB, kZTwoStageThreads>(SingleSrc<ZPushParams<T>>{});
+  zpush_two_stage_body<T, RA, RB, kZTwoStageThreads, SingleSrc<ZPushParams<T>>, PML>(SingleSrc<ZPushParams<T>>{});
 }
 template <typename T, int NTH>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
@@ -1412,8 +1419,12 @@ void launch_two_stage_at(const ZPushParams<T>& p, hipStream_t s) {
   if constexpr (I < (int)(sizeof(kZTwoStage) / sizeof(kZTwoStage[0]))) {
     constexpr int RA = kZTwoStage[I][0], RB = kZTwoStage[I][1];
     if (p.ra == RA && p.rb == RB) {
-      const size_t lds = (size_t)11 * two_stage_slots(RA, RB) * cx_bytes<T>() + (size_t)RA * (RB - 1) * sizeof(Tw<T>);
-      launch_persistent(k_zpush2<T, RA, RB>, p, kZTwoStageThreads, lds, p.ntiles, s);
+      const size_t tw = (size_t)RA * (RB - 1) * sizeof(Tw<T>);
+      const size_t line = (size_t)two_stage_slots(RA, RB) * cx_bytes<T>();
+      if (p.pml)
+        launch_persistent(k_zpush2<T, RA, RB, true>, p, kZTwoStageThreads, 12 * line + tw, p.ntiles, s);
+      else
+        launch_persistent(k_zpush2<T, RA, RB>, p, kZTwoStageThreads, 11 * line + tw, p.ntiles, s);
       return;
     }
     launch_two_stage_at<T, I + 1>(p, s);
@@ -1430,7 +1441,7 @@ extern template void launch_zpush_two_stage<double>(const ZPushParams<double>&, 
 #endif
 template <typename T>
 void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
-  if (p.pml) {  // split-field increments: run-time kernels only
+  if (p.pml && p.ra == 0) {  // split-field increments on the run-time kernels
     if (p.ncol == 1)
       launch_zpush_cols<T, false, true>(p, nthreads, s);
     else

@@ -73,39 +73,41 @@ __device__ __forceinline__ void lin(T s, int& i0, T& w1) {
   w1 = s - f;
 }
 
-__device__ __forceinline__ int wrap(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
+
+// Index i of an axis of n cells folded into [0, n): positions in [0, L) need at most one
+// add or subtract; the clamp keeps out-of-contract positions inside the array.
+__device__ __forceinline__ int fold(int i, int n) {
+  if (i < 0) i += n;
+  if (i >= n) i -= n;
+  return min(max(i, 0), n - 1);
 }
 
-// Field f interpolated at (x, y, z) (lengths), periodic G1.
+// The eight G1 points around (x, y, z) (lengths) of a quantity with half-cell offsets
+// (ox, oy, oz), periodic G1: array offsets and linear weights, corners in (z, y, x) order.
 template <typename T>
-__device__ T gather_one(const T* __restrict__ f, const PicArgs<T>& a, int slot, T x, T y, T z) {
-  const int ox = a.stag ? kOffStag[slot][0] : 0, oy = a.stag ? kOffStag[slot][1] : 0,
-            oz = a.stag ? kOffStag[slot][2] : 0;
+__device__ __forceinline__ void cic_points(const PicArgs<T>& a, T x, T y, T z, int ox, int oy, int oz, int* off,
+                                           T* w) {
   int ix, iy, iz;
   T wx, wy, wz;
   lin(x * a.idx - T(0.5) * ox, ix, wx);
   lin(y * a.idy - T(0.5) * oy, iy, wy);
   lin(z * a.idz - T(0.5) * oz, iz, wz);
+  const int xs[2] = {fold(ix, a.gx), fold(ix + 1, a.gx)};
+  const int ys[2] = {fold(iy, a.gy), fold(iy + 1, a.gy)};
+  const int zs[2] = {fold(iz, a.gz), fold(iz + 1, a.gz)};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+    off[c] = (zs[cz] * a.gy + ys[cy]) * a.gx + xs[cx];
+    w[c] = (cx ? wx : T(1) - wx) * (cy ? wy : T(1) - wy) * (cz ? wz : T(1) - wz);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T gather_at(const T* __restrict__ f, const int* off, const T* w) {
   T acc = 0;
 #pragma unroll
-  for (int cz = 0; cz < 2; ++cz) {
-    const int kz = wrap(iz + cz, a.gz);
-    const T vz = cz ? wz : T(1) - wz;
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy) {
-      const int ky = wrap(iy + cy, a.gy);
-      const T vy = cy ? wy : T(1) - wy;
-      const long long row = ((long long)kz * a.gy + ky) * a.gx;
-#pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const int kx = wrap(ix + cx, a.gx);
-        const T vx = cx ? wx : T(1) - wx;
-        acc += f[row + kx] * (vx * vy * vz);
-      }
-    }
-  }
+  for (int c = 0; c < 8; ++c) acc += f[off[c]] * w[c];
   return acc;
 }
 
@@ -118,16 +120,32 @@ struct PushPtrs {
 };
 
 // Gather E, B at x, relativistic Boris push of u = gamma v, x moved by dt u / gamma (wrapped).
-template <typename T>
+// STAG: staggered grid (each component at its own half-cell offsets); otherwise the six
+// components share one set of points and weights.
+template <typename T, bool STAG>
 __global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs<T> p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const T x = p.x[0][i], y = p.x[1][i], z = p.x[2][i];
   T E[3], B[3];
+  int off[8];
+  T w[8];
+  if constexpr (STAG) {
+    // E_a half a cell up along a; B_a along the two other axes
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    E[k] = gather_one(p.f[k], a, k, x, y, z);
-    B[k] = gather_one(p.f[3 + k], a, 3 + k, x, y, z);
+    for (int k = 0; k < 3; ++k) {
+      cic_points(a, x, y, z, k == 0, k == 1, k == 2, off, w);
+      E[k] = gather_at(p.f[k], off, w);
+      cic_points(a, x, y, z, k != 0, k != 1, k != 2, off, w);
+      B[k] = gather_at(p.f[3 + k], off, w);
+    }
+  } else {
+    cic_points(a, x, y, z, 0, 0, 0, off, w);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      E[k] = gather_at(p.f[k], off, w);
+      B[k] = gather_at(p.f[3 + k], off, w);
+    }
   }
   const T h = T(0.5) * a.qm * a.dt;
   const T ic2 = T(1) / (a.c * a.c);
@@ -494,7 +512,11 @@ int pic_push(psatd_pic* o, void* const* g1, void* const* x, void* const* u, void
     p.u[k] = (T*)u[k];
     p.x_old[k] = (T*)x_old[k];
   }
-  hipLaunchKernelGGL(k_pic_push<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, pic_args<T>(o, n), p);
+  const PicArgs<T> a = pic_args<T>(o, n);
+  if (a.stag)
+    hipLaunchKernelGGL((k_pic_push<T, true>), dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
+  else
+    hipLaunchKernelGGL((k_pic_push<T, false>), dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
   return PSATD_OK;
 }
 

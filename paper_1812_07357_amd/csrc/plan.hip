@@ -781,7 +781,13 @@ void build_step(psatd_plan* p, const StepIO& io, StepParams<T>& sp, bool batched
     z3.fd_ncol = make_fastdiv(nc);
     z3.zgroup = z_group(p->az.sch, p->zthreads, emax<T>::v, sizeof(cx<T>), 12 * nc);
   }
-  if (!batched && !io.pml && (p->two_stage_mask & 4)) two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
+  if (!batched && (p->two_stage_mask & 4)) {
+    two_stage_radices(p, sizeof(cx<T>), &z3.ra, &z3.rb);
+    // PML: the two-stage kernel keeps a twelfth line in LDS
+    if (io.pml && z3.ra &&
+        (size_t)12 * two_stage_slots(z3.ra, z3.rb) * sizeof(cx<T>) + (size_t)z3.ra * (z3.rb - 1) * 16 > lds_limit())
+      z3.ra = z3.rb = 0;
+  }
 
   YPassParams<T>& y4 = sp.y4;
   y4 = YPassParams<T>{};
