@@ -32,9 +32,12 @@ FLAGS = [
 ]
 
 # (source, object name, extra flags).  passes.hip is compiled once per
-# (pass, precision) unit so that the large pass kernels build in parallel.
+# (pass, precision) unit, the run-time z kernels in four units, so that the large pass
+# kernels build in parallel.
 _PASS_UNITS = [(u, name, prec) for u, name in ((1, "xfwd"), (2, "ypass"), (3, "zpush"), (4, "zpush_batch"),
-                                               (5, "xinv"), (6, "zpush_two_stage")) for prec in ("float", "double")]
+                                               (5, "xinv"), (6, "zpush_two_stage"), (7, "zpush_multi"),
+                                               (8, "zpush_pml"), (9, "zpush_pml_multi"))
+               for prec in ("float", "double")]
 SOURCES = [("passes.hip", f"passes_{name}_{prec}", [f"-DPSATD_UNIT={u}", f"-DPSATD_REAL={prec}"])
            for u, name, prec in _PASS_UNITS]
 SOURCES += [(src, os.path.splitext(src)[0], []) for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip", "pic.hip", "pml.hip")]

@@ -1407,13 +1407,33 @@ void launch_ypass(const YPassParams<T>& p, int inverse, hipStream_t s) {
   else
     launch_persistent(k_ypass<-1, T>, p, kLineThreads, ypass_lds(p), p.ntiles, s);
 }
-template <typename T, bool MULTI, bool PML = false>
+template <typename T, bool MULTI, bool PML>
 void launch_zpush_cols(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
   if (nthreads == kZThreads[0])
     launch_persistent(k_zpush<T, kZThreads[0], MULTI, PML>, p, nthreads, zpush_lds(p), p.ntiles, s);
   else
     launch_persistent(k_zpush<T, kZThreads[1], MULTI, PML>, p, nthreads, zpush_lds(p), p.ntiles, s);
 }
+// The run-time z kernels build as four units (single / multi-column, ordinary / PML), in
+// parallel: each unit instantiates one pair, the others only declare it.
+#if defined(PSATD_UNIT)
+#if PSATD_UNIT != 3
+extern template void launch_zpush_cols<float, false, false>(const ZPushParams<float>&, int, hipStream_t);
+extern template void launch_zpush_cols<double, false, false>(const ZPushParams<double>&, int, hipStream_t);
+#endif
+#if PSATD_UNIT != 7
+extern template void launch_zpush_cols<float, true, false>(const ZPushParams<float>&, int, hipStream_t);
+extern template void launch_zpush_cols<double, true, false>(const ZPushParams<double>&, int, hipStream_t);
+#endif
+#if PSATD_UNIT != 8
+extern template void launch_zpush_cols<float, false, true>(const ZPushParams<float>&, int, hipStream_t);
+extern template void launch_zpush_cols<double, false, true>(const ZPushParams<double>&, int, hipStream_t);
+#endif
+#if PSATD_UNIT != 9
+extern template void launch_zpush_cols<float, true, true>(const ZPushParams<float>&, int, hipStream_t);
+extern template void launch_zpush_cols<double, true, true>(const ZPushParams<double>&, int, hipStream_t);
+#endif
+#endif
 template <typename T, int I = 0>
 void launch_two_stage_at(const ZPushParams<T>& p, hipStream_t s) {
   if constexpr (I < (int)(sizeof(kZTwoStage) / sizeof(kZTwoStage[0]))) {
@@ -1453,9 +1473,9 @@ void launch_zpush(const ZPushParams<T>& p, int nthreads, hipStream_t s) {
     return;
   }
   if (p.ncol == 1)
-    launch_zpush_cols<T, false>(p, nthreads, s);
+    launch_zpush_cols<T, false, false>(p, nthreads, s);
   else
-    launch_zpush_cols<T, true>(p, nthreads, s);
+    launch_zpush_cols<T, true, false>(p, nthreads, s);
 }
 template <typename T>
 void launch_xinv(const XInvParams<T>& p, hipStream_t s) {
@@ -1509,7 +1529,11 @@ void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, int nthreads, size_t l
   template size_t ypass_lds<T>(const YPassParams<T>&);
 #define PSATD_INST_3(T)                                                   \
   template void launch_zpush<T>(const ZPushParams<T>&, int, hipStream_t); \
-  template size_t zpush_lds<T>(const ZPushParams<T>&);
+  template size_t zpush_lds<T>(const ZPushParams<T>&);                    \
+  template void launch_zpush_cols<T, false, false>(const ZPushParams<T>&, int, hipStream_t);
+#define PSATD_INST_7(T) template void launch_zpush_cols<T, true, false>(const ZPushParams<T>&, int, hipStream_t);
+#define PSATD_INST_8(T) template void launch_zpush_cols<T, false, true>(const ZPushParams<T>&, int, hipStream_t);
+#define PSATD_INST_9(T) template void launch_zpush_cols<T, true, true>(const ZPushParams<T>&, int, hipStream_t);
 #define PSATD_INST_4(T) \
   template void launch_zpush_batch<T>(const BatchArgs<ZPushParams<T>>&, int, size_t, hipStream_t);
 #define PSATD_INST_6(T) template void launch_zpush_two_stage<T>(const ZPushParams<T>&, hipStream_t);
@@ -1522,8 +1546,9 @@ void launch_xinv_batch(const BatchArgs<XInvParams<T>>& a, int nthreads, size_t l
 #if defined(PSATD_UNIT) && defined(PSATD_REAL)
 PSATD_CAT(PSATD_INST_, PSATD_UNIT)(PSATD_REAL)
 #else
-#define PSATD_INST_ALL(T) \
-  PSATD_INST_1(T) PSATD_INST_2(T) PSATD_INST_3(T) PSATD_INST_4(T) PSATD_INST_5(T) PSATD_INST_6(T)
+#define PSATD_INST_ALL(T)                                                                          \
+  PSATD_INST_1(T) PSATD_INST_2(T) PSATD_INST_3(T) PSATD_INST_4(T) PSATD_INST_5(T) PSATD_INST_6(T) \
+  PSATD_INST_7(T) PSATD_INST_8(T) PSATD_INST_9(T)
 PSATD_INST_ALL(float)
 PSATD_INST_ALL(double)
 #endif

@@ -32,7 +32,7 @@ FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "--offload
 
 def _units():
     out = []
-    for u in range(1, 7):
+    for u in range(1, 10):
         for prec in ("float", "double"):
             out.append(("passes.hip", f"passes_{u}_{prec}", [f"-DPSATD_UNIT={u}", f"-DPSATD_REAL={prec}"]))
     for src in ("tables.hip", "guards.hip", "plan.hip", "mlp.hip", "pic.hip", "pml.hip"):
