@@ -3,7 +3,8 @@
 The oracle (oracle/pml.py) is pinned in tests/test_oracle_pml.py by the ordinary
 box when undamped, the matrix exponential of the split system mode by mode, and
 the absorption of outgoing pulses.  Here the HIP path is compared with it
-element by element over several steps on boxes with even, odd and chirp-z edges,
+element by element over several steps on boxes with even, odd and chirp-z edges and
+with 320 / 256-point lines (the two-stage x kernels and the two-stage PML z kernel),
 layers on one, two or three axes, sources, non-unit c and eps0, FP64 (1e-12
 relative, max norm) and FP32 (2e-6 relative L2 and 2e-5 max norm per step, grown
 linearly with the steps); without layers the sums of the parts equal psatd_push;
@@ -31,7 +32,10 @@ def _check(got, ref, precision, nsteps):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("interior,ng,order,widths", [((40, 36, 30), 0, 8, (6, 0, 0)),
                                                        ((33, 20, 25), 2, 0, (5, 4, 3)),
-                                                       ((47, 16, 18), 0, 16, (0, 3, 4))])
+                                                       ((47, 16, 18), 0, 16, (0, 3, 4)),
+                                                       # x = 320, z = 256: two-stage x kernels and
+                                                       # the two-stage PML z kernel
+                                                       ((320, 12, 256), 0, 16, (16, 2, 24))])
 def test_pml_steps_match_oracle(lib, precision, interior, ng, order, widths):
     import torch
 
