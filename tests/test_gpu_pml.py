@@ -35,7 +35,9 @@ def _check(got, ref, precision, nsteps):
                                                        ((47, 16, 18), 0, 16, (0, 3, 4)),
                                                        # x = 320, z = 256: two-stage x kernels and
                                                        # the two-stage PML z kernel
-                                                       ((320, 12, 256), 0, 16, (16, 2, 24))])
+                                                       ((320, 12, 256), 0, 16, (16, 2, 24)),
+                                                       # z = 180: one column per tile, run-time kernel
+                                                       ((14, 10, 180), 0, 8, (3, 0, 20))])
 def test_pml_steps_match_oracle(lib, precision, interior, ng, order, widths):
     import torch
 
