@@ -205,8 +205,9 @@ int psatd_plan_pass_times(psatd_plan* plan, double ms[5], long long* nsteps);
  * possibly with guards wider than a neighbour, which then come from further
  * sub-domains).  One step advances every box: all guard fills read the fields
  * of the previous step before any interior is written back (Jacobi order,
- * Sec. 2.5.2), and each pass of the step is ONE persistent launch over the
- * tiles of all boxes.
+ * Sec. 2.5.2).  Per pass, the boxes are grouped into classes of equal block
+ * size and similar LDS size, and each class is one persistent launch over the
+ * tiles of its boxes.
  *
  * subs[b] describes box b (interior sizes, guards, order); dx, dy, dz, dt, c,
  * eps0 and precision must agree across boxes.  origins[3*b .. 3*b+2] is the

@@ -1453,8 +1453,8 @@ StepIO g1_io(const psatd_plan* p, void* const* g1, const int origin[3], const in
 // A batch keeps one plan per box.  Binding it to a set of G1 arrays builds the
 // kernel parameters of every box for every pass and uploads them, with the
 // tile offsets, to device memory; each pass of a step is then one persistent
-// launch over all boxes (kernels in passes.hip).  Steps can be replayed from a
-// captured hipGraph.
+// launch per class of boxes with the same block size and a similar LDS size
+// (kernels in passes.hip).  Steps can be replayed from a captured hipGraph.
 struct psatd_batch {
   int nsub = 0;
   int fp64 = 0;

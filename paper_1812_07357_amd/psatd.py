@@ -378,7 +378,8 @@ class Batch:
     ``boxes``: iterable of dicts with ``origin`` (x, y, z), ``interior``
     (nx, ny, nz), ``nguard`` (scalar or triple), ``order`` and optionally
     ``staggered`` (Yee grid, PSATD_FLAG_STAGGERED); ``gdims`` =
-    (GX, GY, GZ).  Each pass of a step is one persistent launch over all boxes;
+    (GX, GY, GZ).  Each pass of a step is one persistent launch per class of boxes
+    (same block size, similar LDS size);
     ``run`` replays ``nsteps`` steps from a captured hipGraph.
     """
 
