@@ -9,9 +9,12 @@ as wide as the interpolation stencil), the Maxwell solve on the FFT boxes of G2
 (decomposition D2), coupled by the guard fill and interior copy of ``domain``.
 
 Readings (the paper fixes none of them):
-* linear (cloud-in-cell) weights; a quantity of a component that sits at
-  offset o (0 or 1/2 cell per axis, kspace.STAGGER_OFFSETS on staggered grids)
-  is attached to the grid points (i + o) d of the periodic grid G1;
+* linear (cloud-in-cell) weights by default; the paper allows higher orders for
+  the deposit and a gather at the same order, read as the centred B-splines of
+  degree 2 (triangular-shaped cloud) and 3 (cubic), ``order`` = 1, 2, 3; a
+  quantity of a component that sits at offset o (0 or 1/2 cell per axis,
+  kspace.STAGGER_OFFSETS on staggered grids) is attached to the grid points
+  (i + o) d of the periodic grid G1;
 * charge density rho = q S / (dx dy dz) at the particles' start and end
   positions, current J = q v S / (dx dy dz) at the mid-point of the step with
   the half-step velocity (not charge-conserving for order-p derivatives; the
@@ -27,45 +30,68 @@ import numpy as np
 from . import kspace
 
 
-def cic(pos, gshape, d, offset=(0, 0, 0)):
-    """Linear weights of particles at ``pos`` (n, 3) (x, y, z lengths) on a periodic grid.
+def shape_1d(s, order: int = 1):
+    """Centred B-spline weights of degree ``order`` at coordinates ``s`` (in cells).
 
-    Returns (idx (n, 8) flat indices into a (nz, ny, nx) array, w (n, 8) weights); the
-    grid point (i, j, k) of a quantity with the given half-cell offsets sits at
-    ((i + ox/2) dx, (j + oy/2) dy, (k + oz/2) dz).
+    Returns (first grid index (n,), weights (n, order + 1)) for the points first .. first+order:
+      1: first = floor(s), f = s - first: (1 - f, f);
+      2: first = round(s) - 1, t = s - round(s) in [-1/2, 1/2):
+         ((1/2 - t)^2 / 2, 3/4 - t^2, (1/2 + t)^2 / 2);
+      3: first = floor(s) - 1, f = s - floor(s):
+         ((1 - f)^3, 4 - 6 f^2 + 3 f^3, 1 + 3 f + 3 f^2 - 3 f^3, f^3) / 6.
+    """
+    s = np.asarray(s, dtype=np.float64)
+    if order == 1:
+        i0 = np.floor(s)
+        f = s - i0
+        return i0.astype(np.int64), np.stack([1.0 - f, f], axis=-1)
+    if order == 2:
+        i0 = np.floor(s + 0.5)
+        t = s - i0
+        return (i0 - 1).astype(np.int64), np.stack([0.5 * (0.5 - t) ** 2, 0.75 - t * t, 0.5 * (0.5 + t) ** 2], axis=-1)
+    if order == 3:
+        i0 = np.floor(s)
+        f = s - i0
+        return (i0 - 1).astype(np.int64), np.stack(
+            [(1 - f) ** 3, 4 - 6 * f * f + 3 * f ** 3, 1 + 3 * f + 3 * f * f - 3 * f ** 3, f ** 3], axis=-1) / 6.0
+    raise ValueError(f"shape order {order} not in 1..3")
+
+
+def cic(pos, gshape, d, offset=(0, 0, 0), order: int = 1):
+    """Weights of particles at ``pos`` (n, 3) (x, y, z lengths) on a periodic grid.
+
+    Returns (idx (n, (order+1)^3) flat indices into a (nz, ny, nx) array, w (same) weights);
+    the grid point (i, j, k) of a quantity with the given half-cell offsets sits at
+    ((i + ox/2) dx, (j + oy/2) dy, (k + oz/2) dz).  Order 1 is cloud in cell.
     """
     nz, ny, nx = gshape
     dx, dy, dz = d
-    xi = np.stack([pos[:, 0] / dx - 0.5 * offset[0], pos[:, 1] / dy - 0.5 * offset[1],
-                   pos[:, 2] / dz - 0.5 * offset[2]], axis=1)
-    i0 = np.floor(xi).astype(np.int64)
-    f = xi - i0
+    fx, wx = shape_1d(pos[:, 0] / dx - 0.5 * offset[0], order)
+    fy, wy = shape_1d(pos[:, 1] / dy - 0.5 * offset[1], order)
+    fz, wz = shape_1d(pos[:, 2] / dz - 0.5 * offset[2], order)
     idx, w = [], []
-    for cz in (0, 1):
-        for cy in (0, 1):
-            for cx in (0, 1):
-                wx = f[:, 0] if cx else 1.0 - f[:, 0]
-                wy = f[:, 1] if cy else 1.0 - f[:, 1]
-                wz = f[:, 2] if cz else 1.0 - f[:, 2]
-                ix = (i0[:, 0] + cx) % nx
-                iy = (i0[:, 1] + cy) % ny
-                iz = (i0[:, 2] + cz) % nz
+    for cz in range(order + 1):
+        for cy in range(order + 1):
+            for cx in range(order + 1):
+                ix = (fx + cx) % nx
+                iy = (fy + cy) % ny
+                iz = (fz + cz) % nz
                 idx.append((iz * ny + iy) * nx + ix)
-                w.append(wx * wy * wz)
+                w.append(wx[:, cx] * wy[:, cy] * wz[:, cz])
     return np.stack(idx, axis=1), np.stack(w, axis=1)
 
 
-def deposit(values, pos, gshape, d, offset=(0, 0, 0)):
+def deposit(values, pos, gshape, d, offset=(0, 0, 0), order: int = 1):
     """Grid array sum_p values_p S(x - pos_p) / (dx dy dz) (periodic), plain scatter-add."""
-    idx, w = cic(pos, gshape, d, offset)
+    idx, w = cic(pos, gshape, d, offset, order)
     out = np.zeros(int(np.prod(gshape)))
     np.add.at(out, idx.ravel(), (w * values[:, None]).ravel() / float(np.prod(d)))
     return out.reshape(gshape)
 
 
-def gather(field, pos, d, offset=(0, 0, 0)):
-    """Field values interpolated at ``pos`` with the same linear weights."""
-    idx, w = cic(pos, field.shape, d, offset)
+def gather(field, pos, d, offset=(0, 0, 0), order: int = 1):
+    """Field values interpolated at ``pos`` with the same weights."""
+    idx, w = cic(pos, field.shape, d, offset, order)
     return np.sum(field.ravel()[idx] * w, axis=1)
 
 
@@ -90,11 +116,12 @@ def boris(u, E, B, q_over_m: float, dt: float, c: float = 1.0):
     return upl + h * E
 
 
-def push(x, u, g1, gshape, d, q_over_m: float, dt: float, c: float = 1.0, staggered: bool = False):
+def push(x, u, g1, gshape, d, q_over_m: float, dt: float, c: float = 1.0, staggered: bool = False,
+         order: int = 1):
     """Gather E, B (slots 0..5 of g1) at x, Boris-push u, move x; returns (x_new, u_new), x wrapped."""
     off = offsets(staggered)
-    E = np.stack([gather(g1[k], x, d, off[k]) for k in range(3)], axis=1)
-    B = np.stack([gather(g1[3 + k], x, d, off[3 + k]) for k in range(3)], axis=1)
+    E = np.stack([gather(g1[k], x, d, off[k], order) for k in range(3)], axis=1)
+    B = np.stack([gather(g1[3 + k], x, d, off[3 + k], order) for k in range(3)], axis=1)
     un = boris(u, E, B, q_over_m, dt, c)
     gam = np.sqrt(1.0 + np.sum(un * un, axis=1, keepdims=True) / (c * c))
     L = np.array([gshape[2] * d[0], gshape[1] * d[1], gshape[0] * d[2]])
@@ -102,7 +129,8 @@ def push(x, u, g1, gshape, d, q_over_m: float, dt: float, c: float = 1.0, stagge
     return xn, un
 
 
-def sources(x_old, x_new, u, q: float, gshape, d, dt: float, c: float = 1.0, staggered: bool = False):
+def sources(x_old, x_new, u, q: float, gshape, d, dt: float, c: float = 1.0, staggered: bool = False,
+            order: int = 1):
     """(J (3, ...), rho_old, rho_new) of particles moving from x_old to x_new with half-step u.
 
     J = q v S at the mid-point x_old + v dt / 2 (v = u / gamma), rho at both ends.
@@ -112,6 +140,6 @@ def sources(x_old, x_new, u, q: float, gshape, d, dt: float, c: float = 1.0, sta
     v = u / gam
     L = np.array([gshape[2] * d[0], gshape[1] * d[1], gshape[0] * d[2]])
     xm = np.mod(x_old + 0.5 * dt * v, L)
-    J = np.stack([deposit(q * v[:, k], xm, gshape, d, off[6 + k]) for k in range(3)])
+    J = np.stack([deposit(q * v[:, k], xm, gshape, d, off[6 + k], order) for k in range(3)])
     qs = np.full(x_old.shape[0], q)
-    return J, deposit(qs, x_old, gshape, d, off[9]), deposit(qs, x_new, gshape, d, off[10])
+    return J, deposit(qs, x_old, gshape, d, off[9], order), deposit(qs, x_new, gshape, d, off[10], order)

@@ -137,3 +137,58 @@ def test_sources_of_resting_and_moving_particles():
     assert abs(J[0].sum() - 50 * 0.2 * v) <= 1e-12
     assert abs(J[1]).max() == 0.0 and abs(J[2]).max() == 0.0
     assert abs(r1.sum() - r0.sum()) <= 1e-12
+
+
+def _bspline(x, k):
+    """Centred cardinal B-spline of degree k from the truncated-power formula
+    B(x) = (1/k!) sum_j (-1)^j C(k+1, j) (x + (k+1)/2 - j)_+^k (independent of shape_1d)."""
+    from math import comb, factorial
+
+    out = np.zeros_like(x, dtype=np.float64)
+    for j in range(k + 2):
+        t = x + 0.5 * (k + 1) - j
+        out += (-1) ** j * comb(k + 1, j) * np.where(t > 0, t, 0.0) ** k
+    return out / factorial(k)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_shape_weights_equal_the_centred_b_spline(order):
+    rng = synth.rng_for(155, order)
+    s = np.concatenate([rng.uniform(-3.0, 7.0, 400), [0.0, 0.5, 1.0, -0.5, 2.25]])
+    first, w = pic.shape_1d(s, order)
+    for p in range(len(s)):
+        i = np.arange(first[p] - 2, first[p] + order + 3)
+        ref = _bspline(s[p] - i, order)
+        got = np.zeros_like(ref)
+        got[2:2 + order + 1] = w[p]
+        np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_shape_moments(order):
+    """sum w = 1 and sum w (i - s) = 0 for every position; for degree >= 2, which reproduces
+    quadratics, also sum w (i - s)^2 = (order + 1) / 12, the B-spline's variance."""
+    s = synth.rng_for(156, order).uniform(-5.0, 5.0, 1000)
+    first, w = pic.shape_1d(s, order)
+    i = first[:, None] + np.arange(order + 1)[None, :]
+    np.testing.assert_allclose(w.sum(1), 1.0, atol=1e-14)
+    np.testing.assert_allclose((w * (i - s[:, None])).sum(1), 0.0, atol=1e-13)
+    if order >= 2:
+        np.testing.assert_allclose((w * (i - s[:, None]) ** 2).sum(1), (order + 1) / 12.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_higher_order_deposit_conserves_charge_and_is_adjoint(order):
+    gshape, d = (8, 6, 10), (1.0, 0.8, 1.2)
+    rng = synth.rng_for(157, order)
+    L = np.array([gshape[2] * d[0], gshape[1] * d[1], gshape[0] * d[2]])
+    pos = rng.uniform(0, 1, size=(300, 3)) * L
+    q = rng.normal(size=300)
+    vol = np.prod(d)
+    for off in ((0, 0, 0), (1, 0, 1)):
+        rho = pic.deposit(q, pos, gshape, d, off, order)
+        assert abs(rho.sum() * vol - q.sum()) <= 1e-12 * np.abs(q).sum()
+        F = rng.normal(size=gshape)
+        lhs = float(np.sum(F * rho) * vol)
+        rhs = float(np.sum(q * pic.gather(F, pos, d, off, order)))
+        assert abs(lhs - rhs) <= 1e-12 * np.abs(q).sum() * np.abs(F).max()
