@@ -379,8 +379,8 @@ int psatd_pml_step(psatd_plan* plan, void* const* parts, const void* const* src,
 /* ---------------------------------------------------------------- particles
  * The particle side of the PIC cycle around the step (Sec. 2.5.1, Fig. 4:
  * push the particles with the fields at their positions, deposit their current
- * and charge with linear interpolation, solve Maxwell's equations, gather the
- * new fields back).  Particle-mesh work runs on the global grid G1 cut into
+ * and charge with linear or higher-order interpolation, solve Maxwell's
+ * equations, gather the new fields back at the same order).  Particle-mesh work runs on the global grid G1 cut into
  * sub-domains D1 whose guard cells are as wide as the stencil (Sec. 2.5.2):
  * here a D1 sub-domain is a tile of tile^3 cells handled by one workgroup,
  * whose guard contributions are added into the neighbouring tiles' cells.
@@ -391,8 +391,14 @@ int psatd_pml_step(psatd_plan* plan, void* const* parts, const void* const* src,
  * the collocated grid; PSATD_FLAG_STAGGERED: the Yee offsets of the plan flag,
  * J like E, rho on the nodes) has its array index i at (i + o/2) d; the grid is
  * periodic with lengths L = (gx dx, gy dy, gz dz).  A particle at x takes part
- * in the 2 x 2 x 2 points around x - o d/2 with the product of the 1D linear
- * weights (cloud in cell).  Particles are structure-of-arrays: x[0..2] the
+ * in the (k+1)^3 points around s = (x - o d/2) / d with the product of the 1D
+ * centred B-spline weights of degree k = shape (Sec. 2.5.1):
+ *   k = 1 (cloud in cell): points floor(s) + {0, 1}, weights 1 - t, t (t = s - floor(s));
+ *   k = 2 (triangular-shaped cloud): points round(s) + {-1, 0, 1}, t = s - round(s),
+ *         weights (1/2 - t)^2 / 2, 3/4 - t^2, (1/2 + t)^2 / 2;
+ *   k = 3 (cubic): points floor(s) + {-1, 0, 1, 2}, t = s - floor(s), weights
+ *         (1 - t)^3 / 6, (4 - 6t^2 + 3t^3) / 6, (1 + 3t + 3t^2 - 3t^3) / 6, t^3 / 6.
+ * Gather and deposit use the same shape.  Particles are structure-of-arrays: x[0..2] the
  * positions (x, y, z), u[0..2] the momentum per mass u = gamma v, n values each
  * (device arrays of the object's precision).  Positions lie in [0, L). */
 typedef struct {
@@ -405,13 +411,16 @@ typedef struct {
   int tile;          /* D1 tile edge in cells, 1..12; 8 is a good default */
   int precision;     /* PSATD_FP32 or PSATD_FP64 */
   int flags;         /* 0 or PSATD_FLAG_STAGGERED */
+  int shape;         /* degree of the particle shape: 1, 2 or 3 (0 means 1) */
 } psatd_pic_desc;
 typedef struct psatd_pic psatd_pic;
 
 /* Checks the descriptor and allocates the per-tile lists (12 bytes per tile
- * + 4 bytes per particle).  A tile accumulates over itself, one guard cell
- * below and two above per axis: the reach of the linear stencil of a particle
- * that started in the tile and moved less than a cell.  PSATD_EUNSUPPORTED if
+ * + 4 bytes per particle).  A tile accumulates over itself and guard cells per
+ * axis, one below and two above for shape 1, two below and three above for
+ * shapes 2 and 3: the reach of the stencil of a particle that started in the
+ * tile and moved less than a cell (tile 8: 11^3 or 13^3 cells, 53 or 88 KB of
+ * LDS).  PSATD_EUNSUPPORTED if
  * c dt exceeds 0.999 of the smallest cell size (a particle could then leave
  * those guard cells within one step; the margin absorbs the rounding of
  * positions) or the tile's LDS block does not fit the device. */

@@ -12,18 +12,20 @@
 // Here a D1 sub-domain is a tile of T^3 cells of G1 worked on by one workgroup:
 // the particles are counted per tile (by their start position), the tile
 // offsets scanned, the particles listed per tile, and each workgroup deposits its
-// tile's particles into LDS over the tile plus its guard cells (kGuardLo below,
-// kGuardHi above, per axis), then adds that LDS block into G1 (the guard cells land
+// tile's particles into LDS over the tile plus its guard cells (Reach<K>::lo below,
+// Reach<K>::hi above, per axis), then adds that LDS block into G1 (the guard cells land
 // on the neighbouring tiles' cells: the additive guard merge of the D1
-// decomposition).  The guards hold the linear stencil of a particle that started in
+// decomposition).  The guards hold the stencil of a particle that started in
 // the tile and moved less than one cell during the step, which the host ensures
 // (c dt below the smallest cell size, with a margin for rounding).  The LDS block sums in
 // 64-bit fixed point with a power-of-two scale per tile, so a tile's sums are exact and do
 // not depend on the order of the atomics.
 //
 // Weights: a quantity of a component with half-cell offset o sits at grid point
-// (i + o/2) d; a particle at x spreads over the 2 x 2 x 2 points around it with
-// the product of the 1D linear weights (cloud in cell).  rho = q S / (dx dy dz)
+// (i + o/2) d; a particle at x spreads over the (K+1)^3 points around it with the
+// product of the 1D centred B-spline weights of degree K (Sec. 2.5.1 allows linear or
+// higher-order interpolation: K = 1 cloud in cell, 2 triangular-shaped cloud, 3 cubic),
+// and the gather uses the same weights.  rho = q S / (dx dy dz)
 // at the start and end positions, J = q v S / (dx dy dz) at the mid-point with
 // the half-step velocity.
 
@@ -40,10 +42,14 @@ namespace psatd {
 namespace {
 
 constexpr int kPicThreads = 256;
-// Stencil reach of a particle that starts in cell c and moves less than one cell: the
-// points of rho_new and of J (mid-point, half a cell away) span [c - 1, c + 2].
-constexpr int kGuardLo = 1;
-constexpr int kGuardHi = 2;
+// Stencil reach of a particle that starts in cell c and moves less than one cell, for
+// weights of degree K: the points of rho_new and of J (mid-point, half a cell away) span
+// [c - 1, c + 2] (K = 1) or [c - 2, c + 3] (K = 2, 3).
+template <int K>
+struct Reach {
+  static constexpr int lo = K == 1 ? 1 : 2, hi = K == 1 ? 2 : 3;
+};
+constexpr int kMaxShape = 3;
 // c dt may reach this fraction of the smallest cell (the rest absorbs rounding).
 constexpr double kMaxCourant = 0.999;
 constexpr int kTileMax = 12;
@@ -65,12 +71,29 @@ struct PicArgs {
   int n;
 };
 
-// Linear weights of coordinate s (in cells) around grid index i0 = floor(s).
-template <typename T>
-__device__ __forceinline__ void lin(T s, int& i0, T& w1) {
-  const T f = floor(s);
-  i0 = (int)f;
-  w1 = s - f;
+// Centred B-spline weights of degree K of coordinate s (in cells): the K + 1 points
+// first, ..., first + K and their weights.
+template <int K, typename T>
+__device__ __forceinline__ void shape1d(T s, int& first, T* w) {
+  if constexpr (K == 1) {
+    const T f = floor(s), t = s - f;
+    first = (int)f;
+    w[0] = T(1) - t;
+    w[1] = t;
+  } else if constexpr (K == 2) {
+    const T r = floor(s + T(0.5)), t = s - r;
+    first = (int)r - 1;
+    w[0] = T(0.5) * (T(0.5) - t) * (T(0.5) - t);
+    w[1] = T(0.75) - t * t;
+    w[2] = T(0.5) * (T(0.5) + t) * (T(0.5) + t);
+  } else {
+    const T f = floor(s), t = s - f, t2 = t * t, t3 = t2 * t, u = T(1) - t;
+    first = (int)f - 1;
+    w[0] = u * u * u / T(6);
+    w[1] = (T(4) - T(6) * t2 + T(3) * t3) / T(6);
+    w[2] = (T(1) + T(3) * t + T(3) * t2 - T(3) * t3) / T(6);
+    w[3] = t3 / T(6);
+  }
 }
 
 
@@ -82,32 +105,41 @@ __device__ __forceinline__ int fold(int i, int n) {
   return min(max(i, 0), n - 1);
 }
 
-// The eight G1 points around (x, y, z) (lengths) of a quantity with half-cell offsets
-// (ox, oy, oz), periodic G1: array offsets and linear weights, corners in (z, y, x) order.
-template <typename T>
-__device__ __forceinline__ void cic_points(const PicArgs<T>& a, T x, T y, T z, int ox, int oy, int oz, int* off,
-                                           T* w) {
-  int ix, iy, iz;
-  T wx, wy, wz;
-  lin(x * a.idx - T(0.5) * ox, ix, wx);
-  lin(y * a.idy - T(0.5) * oy, iy, wy);
-  lin(z * a.idz - T(0.5) * oz, iz, wz);
-  const int xs[2] = {fold(ix, a.gx), fold(ix + 1, a.gx)};
-  const int ys[2] = {fold(iy, a.gy), fold(iy + 1, a.gy)};
-  const int zs[2] = {fold(iz, a.gz), fold(iz + 1, a.gz)};
+// The (K+1)^3 G1 points around (x, y, z) (lengths) of a quantity with half-cell offsets
+// (ox, oy, oz), periodic G1, as per-axis folded indices and weights.
+template <int K, typename T>
+struct Points {
+  int xs[K + 1], ys[K + 1], zs[K + 1];
+  T wx[K + 1], wy[K + 1], wz[K + 1];
+};
+
+template <int K, typename T>
+__device__ __forceinline__ void grid_points(Points<K, T>& g, const PicArgs<T>& a, T x, T y, T z, int ox, int oy,
+                                            int oz) {
+  int fx, fy, fz;
+  shape1d<K>(x * a.idx - T(0.5) * ox, fx, g.wx);
+  shape1d<K>(y * a.idy - T(0.5) * oy, fy, g.wy);
+  shape1d<K>(z * a.idz - T(0.5) * oz, fz, g.wz);
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-    off[c] = (zs[cz] * a.gy + ys[cy]) * a.gx + xs[cx];
-    w[c] = (cx ? wx : T(1) - wx) * (cy ? wy : T(1) - wy) * (cz ? wz : T(1) - wz);
+  for (int c = 0; c <= K; ++c) {
+    g.xs[c] = fold(fx + c, a.gx);
+    g.ys[c] = fold(fy + c, a.gy) * a.gx;
+    g.zs[c] = fold(fz + c, a.gz) * a.gy * a.gx;
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T gather_at(const T* __restrict__ f, const int* off, const T* w) {
+template <int K, typename T>
+__device__ __forceinline__ T gather_at(const T* __restrict__ f, const Points<K, T>& g) {
   T acc = 0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc += f[off[c]] * w[c];
+  for (int cz = 0; cz <= K; ++cz)
+#pragma unroll
+    for (int cy = 0; cy <= K; ++cy) {
+      const T wyz = g.wy[cy] * g.wz[cz];
+      const int row = g.zs[cz] + g.ys[cy];
+#pragma unroll
+      for (int cx = 0; cx <= K; ++cx) acc += f[row + g.xs[cx]] * (g.wx[cx] * wyz);
+    }
   return acc;
 }
 
@@ -122,29 +154,28 @@ struct PushPtrs {
 // Gather E, B at x, relativistic Boris push of u = gamma v, x moved by dt u / gamma (wrapped).
 // STAG: staggered grid (each component at its own half-cell offsets); otherwise the six
 // components share one set of points and weights.
-template <typename T, bool STAG>
+template <typename T, bool STAG, int K>
 __global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs<T> p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const T x = p.x[0][i], y = p.x[1][i], z = p.x[2][i];
   T E[3], B[3];
-  int off[8];
-  T w[8];
+  Points<K, T> g;
   if constexpr (STAG) {
     // E_a half a cell up along a; B_a along the two other axes
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      cic_points(a, x, y, z, k == 0, k == 1, k == 2, off, w);
-      E[k] = gather_at(p.f[k], off, w);
-      cic_points(a, x, y, z, k != 0, k != 1, k != 2, off, w);
-      B[k] = gather_at(p.f[3 + k], off, w);
+      grid_points<K>(g, a, x, y, z, k == 0, k == 1, k == 2);
+      E[k] = gather_at<K>(p.f[k], g);
+      grid_points<K>(g, a, x, y, z, k != 0, k != 1, k != 2);
+      B[k] = gather_at<K>(p.f[3 + k], g);
     }
   } else {
-    cic_points(a, x, y, z, 0, 0, 0, off, w);
+    grid_points<K>(g, a, x, y, z, 0, 0, 0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      E[k] = gather_at(p.f[k], off, w);
-      B[k] = gather_at(p.f[3 + k], off, w);
+      E[k] = gather_at<K>(p.f[k], g);
+      B[k] = gather_at<K>(p.f[3 + k], g);
     }
   }
   const T h = T(0.5) * a.qm * a.dt;
@@ -279,10 +310,42 @@ __global__ void __launch_bounds__(kPicThreads) k_tile_list(PicArgs<T> a, DepPtrs
   if (active) p.list[base + (int)__lane_id() - r.leader] = i;
 }
 
-// The linear stencil of one quantity of one particle inside the LDS block of a tile: the
-// block-local index of its lower corner and the eight weighted values, corners in (z, y, x)
-// order.  The block spans E = T + kGuardLo + kGuardHi cells per axis from the tile's first
-// cell (bx, by, bz) minus kGuardLo.
+// The stencil of one quantity of one particle inside the LDS block of a tile, in
+// separable form: the block-local index of its first point and the 1D weights per axis
+// (the value folded into the x weights).  The block spans E = T + Reach<K>::lo +
+// Reach<K>::hi cells per axis from the tile's first cell (bx, by, bz) minus Reach<K>::lo.
+template <int K, typename T>
+struct Axes {
+  int l0;
+  T wx[K + 1], wy[K + 1], wz[K + 1];
+};
+
+template <int K, typename T>
+__device__ __forceinline__ void stencil_axes(Axes<K, T>& s, int E, const PicArgs<T>& a, int slot, T x, T y, T z,
+                                             T value, int bx, int by, int bz) {
+  const int ox = a.stag ? kOffStag[slot][0] : 0, oy = a.stag ? kOffStag[slot][1] : 0,
+            oz = a.stag ? kOffStag[slot][2] : 0;
+  int ix, iy, iz;
+  shape1d<K>(x * a.idx - T(0.5) * ox, ix, s.wx);
+  shape1d<K>(y * a.idy - T(0.5) * oy, iy, s.wy);
+  shape1d<K>(z * a.idz - T(0.5) * oz, iz, s.wz);
+#pragma unroll
+  for (int c = 0; c <= K; ++c) s.wx[c] *= value;
+  // local indices relative to the block origin (tile origin - guard); positions near the
+  // periodic edge are taken on the tile's side of the edge.  For positions in [0, L) whose
+  // particle started in the tile the first point lies in [0, E - 1 - K]; the clamp only
+  // keeps positions that break that contract inside the block.
+  auto local = [&](int i, int b, int n) {
+    int l = i - (b - Reach<K>::lo);
+    if (l < 0) l += n;
+    if (l >= n) l -= n;
+    return min(max(l, 0), E - 1 - K);
+  };
+  s.l0 = (local(iz, bz, a.gz) * E + local(iy, by, a.gy)) * E + local(ix, bx, a.gx);
+}
+
+// The linear stencil as eight weighted values, corners in (z, y, x) order: the form the
+// run accumulation below sums in registers.
 template <typename T>
 struct Stencil {
   int l0;
@@ -292,29 +355,11 @@ struct Stencil {
 template <typename T>
 __device__ __forceinline__ void stencil(Stencil<T>& s, int E, const PicArgs<T>& a, int slot, T x, T y, T z,
                                         T value, int bx, int by, int bz) {
-  const int ox = a.stag ? kOffStag[slot][0] : 0, oy = a.stag ? kOffStag[slot][1] : 0,
-            oz = a.stag ? kOffStag[slot][2] : 0;
-  int ix, iy, iz;
-  T wx, wy, wz;
-  lin(x * a.idx - T(0.5) * ox, ix, wx);
-  lin(y * a.idy - T(0.5) * oy, iy, wy);
-  lin(z * a.idz - T(0.5) * oz, iz, wz);
-  // local indices relative to the block origin (tile origin - guard); positions near the
-  // periodic edge are taken on the tile's side of the edge.  For positions in [0, L) whose
-  // particle started in the tile the index lies in [0, T + 1]; the clamp only keeps
-  // positions that break that contract inside the block.
-  auto local = [&](int i, int b, int n) {
-    int l = i - (b - kGuardLo);
-    if (l < 0) l += n;
-    if (l >= n) l -= n;
-    return min(max(l, 0), E - 2);
-  };
-  s.l0 = (local(iz, bz, a.gz) * E + local(iy, by, a.gy)) * E + local(ix, bx, a.gx);
+  Axes<1, T> g;
+  stencil_axes<1>(g, E, a, slot, x, y, z, value, bx, by, bz);
+  s.l0 = g.l0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const T vx = (c & 1) ? wx : T(1) - wx, vy = (c & 2) ? wy : T(1) - wy, vz = (c & 4) ? wz : T(1) - wz;
-    s.w[c] = value * (vx * vy * vz);
-  }
+  for (int c = 0; c < 8; ++c) s.w[c] = g.wx[c & 1] * (g.wy[(c >> 1) & 1] * g.wz[c >> 2]);
 }
 
 // The LDS block accumulates in 64-bit fixed point: each weighted value times a power of two
@@ -330,6 +375,21 @@ __device__ __forceinline__ void stencil_add(fixed_t* blk, int E, const Stencil<T
     const long long v = llrint((double)(s.w[c] * scale));
     atomicAdd(&blk[s.l0 + ((c >> 2) * E + ((c >> 1) & 1)) * E + (c & 1)], (fixed_t)v);
   }
+}
+
+// A stencil of degree K > 1 straight into the block, (K + 1)^3 atomics (its weights do not
+// fit a register run).
+template <int K, typename T>
+__device__ __forceinline__ void stencil_add_axes(fixed_t* blk, int E, const Axes<K, T>& s, T scale) {
+#pragma unroll
+  for (int cz = 0; cz <= K; ++cz)
+#pragma unroll
+    for (int cy = 0; cy <= K; ++cy) {
+      const T wyz = s.wy[cy] * s.wz[cz] * scale;
+      fixed_t* row = blk + s.l0 + (cz * E + cy) * E;
+#pragma unroll
+      for (int cx = 0; cx <= K; ++cx) atomicAdd(&row[cx], (fixed_t)llrint((double)(s.wx[cx] * wyz)));
+    }
 }
 
 // Running sum of the stencils of consecutive particles of one thread: particles whose
@@ -348,11 +408,12 @@ __device__ __forceinline__ void stencil_run(fixed_t* blk, int E, Stencil<T>& acc
 
 // One workgroup per D1 tile: its particles' J (mid-point), rho_old (start) and rho_new
 // (end) into LDS over the tile and its guard cells, then the block added into G1.
-template <typename T>
+template <typename T, int K>
 __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, DepPtrs<T> p) {
   extern __shared__ double2 pic_smem[];
   fixed_t* lds = reinterpret_cast<fixed_t*>(pic_smem);
-  const int E = a.tile + kGuardLo + kGuardHi;
+  constexpr int GL = Reach<K>::lo;
+  const int E = a.tile + GL + Reach<K>::hi;
   const int ncl = E * E * E;
   const int tid = threadIdx.x;
   // merge walk: thread (row r0, column lx) of R = blockDim / E rows per round
@@ -380,9 +441,9 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
     const T sj = (T)ldexp(1.0, ejc), sr = (T)ldexp(1.0, erc);
     const int per = (count + (int)blockDim.x - 1) / (int)blockDim.x;
     const int e0 = first + min(count, tid * per), e1 = first + min(count, (tid + 1) * per);
-    Stencil<T> acc[5], cur;
+    Stencil<T> acc[K == 1 ? 5 : 1], cur;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) acc[q].l0 = -1;
+    for (int q = 0; q < (K == 1 ? 5 : 1); ++q) acc[q].l0 = -1;
     for (int e = e0; e < e1; ++e) {
       const int i = p.list[e];
       const T u0 = p.u[0][i], u1 = p.u[1][i], u2 = p.u[2][i];
@@ -394,19 +455,34 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
       xm -= a.lx * floor(xm / a.lx);
       ym -= a.ly * floor(ym / a.ly);
       zm -= a.lz * floor(zm / a.lz);
+      if constexpr (K == 1) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        stencil(cur, E, a, 6 + k, xm, ym, zm, qv * v[k], bx, by, bz);
-        stencil_run(lds + k * ncl, E, acc[k], cur, sj);
+        for (int k = 0; k < 3; ++k) {
+          stencil(cur, E, a, 6 + k, xm, ym, zm, qv * v[k], bx, by, bz);
+          stencil_run(lds + k * ncl, E, acc[k], cur, sj);
+        }
+        stencil(cur, E, a, 9, x0, y0, z0, qv, bx, by, bz);
+        stencil_run(lds + 3 * ncl, E, acc[3], cur, sr);
+        stencil(cur, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
+        stencil_run(lds + 4 * ncl, E, acc[4], cur, sr);
+      } else {
+        Axes<K, T> g;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          stencil_axes<K>(g, E, a, 6 + k, xm, ym, zm, qv * v[k], bx, by, bz);
+          stencil_add_axes<K>(lds + k * ncl, E, g, sj);
+        }
+        stencil_axes<K>(g, E, a, 9, x0, y0, z0, qv, bx, by, bz);
+        stencil_add_axes<K>(lds + 3 * ncl, E, g, sr);
+        stencil_axes<K>(g, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
+        stencil_add_axes<K>(lds + 4 * ncl, E, g, sr);
       }
-      stencil(cur, E, a, 9, x0, y0, z0, qv, bx, by, bz);
-      stencil_run(lds + 3 * ncl, E, acc[3], cur, sr);
-      stencil(cur, E, a, 10, p.xn[0][i], p.xn[1][i], p.xn[2][i], qv, bx, by, bz);
-      stencil_run(lds + 4 * ncl, E, acc[4], cur, sr);
     }
+    if constexpr (K == 1) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
-      if (acc[q].l0 >= 0) stencil_add(lds + q * ncl, E, acc[q], q < 3 ? sj : sr);
+      for (int q = 0; q < 5; ++q)
+        if (acc[q].l0 >= 0) stencil_add(lds + q * ncl, E, acc[q], q < 3 ? sj : sr);
+    }
     __syncthreads();
     // the block (tile and guards) added into G1: guard cells are the neighbours' cells.
     // Rows (f, z, y) are walked with carries, so no element needs a division.
@@ -419,13 +495,13 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
         }
         return v;
       };
-      const int gxi = wrap_near(bx - kGuardLo + lx, a.gx);
+      const int gxi = wrap_near(bx - GL + lx, a.gx);
       int y = r0 % E, z = (r0 / E) % E, f = r0 / (E * E);
       while (f < 5) {
         const long long iv = (long long)lds[((f * E + z) * E + y) * E + lx];
         if (iv != 0) {
           const T v = (T)((double)iv * ldexp(1.0, -(f < 3 ? ejc : erc)));
-          const int gyi = wrap_near(by - kGuardLo + y, a.gy), gzi = wrap_near(bz - kGuardLo + z, a.gz);
+          const int gyi = wrap_near(by - GL + y, a.gy), gzi = wrap_near(bz - GL + z, a.gz);
           unsafeAtomicAdd(&p.g[f][((long long)gzi * a.gy + gyi) * a.gx + gxi], v);
         }
         y += dy;
@@ -493,11 +569,15 @@ PicArgs<T> pic_args(const psatd_pic* o, int n) {
   return a;
 }
 
-// LDS of one deposit workgroup: five fixed-point quantities over the tile and its guard cells.
-size_t pic_lds_bytes(int tile) {
-  const size_t e = (size_t)tile + kGuardLo + kGuardHi;
+// LDS of one deposit workgroup: five fixed-point quantities over the tile and its guard
+// cells, for particle shapes of degree `shape`.
+size_t pic_lds_bytes(int tile, int shape) {
+  const size_t e = (size_t)tile + (shape == 1 ? Reach<1>::lo + Reach<1>::hi : Reach<2>::lo + Reach<2>::hi);
   return 5 * e * e * e * sizeof(fixed_t);
 }
+
+// degree of the particle shape of a descriptor (0 means linear)
+int shape_of(const psatd_pic_desc& d) { return d.shape == 0 ? 1 : d.shape; }
 
 unsigned blocks_for(long long n, int th) { return (unsigned)((n + th - 1) / th); }
 
@@ -513,11 +593,26 @@ int pic_push(psatd_pic* o, void* const* g1, void* const* x, void* const* u, void
     p.x_old[k] = (T*)x_old[k];
   }
   const PicArgs<T> a = pic_args<T>(o, n);
-  if (a.stag)
-    hipLaunchKernelGGL((k_pic_push<T, true>), dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
-  else
-    hipLaunchKernelGGL((k_pic_push<T, false>), dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
+  const dim3 grid(blocks_for(n, kPicThreads)), block(kPicThreads);
+  switch (shape_of(o->d) * 2 + a.stag) {
+    case 2: hipLaunchKernelGGL((k_pic_push<T, false, 1>), grid, block, 0, s, a, p); break;
+    case 3: hipLaunchKernelGGL((k_pic_push<T, true, 1>), grid, block, 0, s, a, p); break;
+    case 4: hipLaunchKernelGGL((k_pic_push<T, false, 2>), grid, block, 0, s, a, p); break;
+    case 5: hipLaunchKernelGGL((k_pic_push<T, true, 2>), grid, block, 0, s, a, p); break;
+    case 6: hipLaunchKernelGGL((k_pic_push<T, false, 3>), grid, block, 0, s, a, p); break;
+    default: hipLaunchKernelGGL((k_pic_push<T, true, 3>), grid, block, 0, s, a, p); break;
+  }
   return PSATD_OK;
+}
+
+template <typename T, int K>
+void launch_deposit(const PicArgs<T>& a, const DepPtrs<T>& p, int ntiles, size_t lds, hipStream_t s) {
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_deposit_tiles<T, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  // one tile per workgroup (the loop inside covers grids beyond the cap)
+  const unsigned grid = (unsigned)std::min(ntiles, 1 << 20);
+  hipLaunchKernelGGL((k_deposit_tiles<T, K>), dim3(grid), dim3(kPicThreads), lds, s, a, p);
 }
 
 template <typename T>
@@ -542,12 +637,14 @@ int pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const v
   hipLaunchKernelGGL(k_tile_count<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, o->count, o->offset, o->cursor, o->ntiles);
   hipLaunchKernelGGL(k_tile_list<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
-  const size_t lds = pic_lds_bytes(o->d.tile);
-  if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_deposit_tiles<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  // one tile per workgroup (the loop inside covers grids beyond the cap)
-  const unsigned grid = (unsigned)std::min(o->ntiles, 1 << 20);
-  hipLaunchKernelGGL(k_deposit_tiles<T>, dim3(grid), dim3(kPicThreads), lds, s, a, p);
+  const int shape = shape_of(o->d);
+  const size_t lds = pic_lds_bytes(o->d.tile, shape);
+  if (shape == 1)
+    launch_deposit<T, 1>(a, p, o->ntiles, lds, s);
+  else if (shape == 2)
+    launch_deposit<T, 2>(a, p, o->ntiles, lds, s);
+  else
+    launch_deposit<T, 3>(a, p, o->ntiles, lds, s);
   return PSATD_OK;
 }
 
@@ -566,6 +663,8 @@ int psatd_pic_create(const psatd_pic_desc* d, psatd_pic** out) {
   if (d->flags & ~PSATD_FLAG_STAGGERED) return report_error(PSATD_EINVAL, "unknown flags 0x%x", d->flags);
   if (d->tile < 1 || d->tile > kTileMax) return report_error(PSATD_EINVAL, "tile must be in [1, %d]", kTileMax);
   if (d->max_particles < 0) return report_error(PSATD_EINVAL, "max_particles must be >= 0");
+  if (d->shape < 0 || d->shape > kMaxShape)
+    return report_error(PSATD_EINVAL, "shape must be 0 (linear), 1, 2 or %d", kMaxShape);
   // a particle moves less than c dt per step; the margin covers the rounding of positions
   if (d->c * d->dt > kMaxCourant * std::min(d->dx, std::min(d->dy, d->dz)))
     return report_error(PSATD_EUNSUPPORTED,
@@ -579,10 +678,10 @@ int psatd_pic_create(const psatd_pic_desc* d, psatd_pic** out) {
       (void)hipGetLastError();
       lim = 64 * 1024;
     }
-    const size_t need = pic_lds_bytes(d->tile);
+    const size_t need = pic_lds_bytes(d->tile, shape_of(*d));
     if (need > (size_t)lim)
-      return report_error(PSATD_EUNSUPPORTED, "tile %d needs %zu bytes of LDS per workgroup (limit %d)", d->tile,
-                          need, lim);
+      return report_error(PSATD_EUNSUPPORTED, "tile %d with shape degree %d needs %zu bytes of LDS per workgroup "
+                          "(limit %d)", d->tile, shape_of(*d), need, lim);
   }
   psatd_pic* o = new psatd_pic;
   o->d = *d;

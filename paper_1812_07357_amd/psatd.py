@@ -46,6 +46,7 @@ class PicDesc(ctypes.Structure):
         ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
         ("dt", ctypes.c_double), ("c", ctypes.c_double), ("q", ctypes.c_double), ("q_over_m", ctypes.c_double),
         ("max_particles", ctypes.c_int), ("tile", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
+        ("shape", ctypes.c_int),
     ]
 
 
@@ -448,25 +449,28 @@ class Batch:
 class Pic:
     """Particle side of the PIC cycle on the global grid G1 (psatd_pic_*).
 
-    ``gdims`` = (GX, GY, GZ); ``tile`` the D1 tile edge; particles are
-    (3, n) tensors of positions ``x`` and momenta per mass ``u`` (x, y, z rows),
-    of the object's precision, on the GPU.
+    ``gdims`` = (GX, GY, GZ); ``tile`` the D1 tile edge; ``shape`` the degree
+    of the particle shape (1 cloud in cell, 2 triangular-shaped cloud, 3 cubic
+    B-spline) used by both gather and deposit; particles are (3, n) tensors of
+    positions ``x`` and momenta per mass ``u`` (x, y, z rows), of the object's
+    precision, on the GPU.
     """
 
     def __init__(self, gdims, dx=1.0, dt=0.5, c=1.0, q=1.0, q_over_m=1.0, max_particles=1 << 20, tile=8,
-                 precision="fp32", staggered=False):
+                 precision="fp32", staggered=False, shape=1):
         import torch
 
         d = _triple(dx)
         desc = PicDesc(int(gdims[0]), int(gdims[1]), int(gdims[2]), float(d[0]), float(d[1]), float(d[2]),
                        float(dt), float(c), float(q), float(q_over_m), int(max_particles), int(tile),
                        PSATD_FP64 if precision == "fp64" else PSATD_FP32,
-                       PSATD_FLAG_STAGGERED if staggered else 0)
+                       PSATD_FLAG_STAGGERED if staggered else 0, int(shape))
         h = ctypes.c_void_p()
         _check(_lib.psatd_pic_create(ctypes.byref(desc), ctypes.byref(h)))
         self._h = h
         self.gdims = tuple(int(v) for v in gdims)
         self.max_particles = int(max_particles)
+        self.shape = int(shape) if shape else 1
         self.precision = "fp64" if precision == "fp64" else "fp32"
         self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
 

@@ -141,6 +141,9 @@ int main(int argc, char** argv) {
     psatd_pic* o = NULL;
     CHECK(psatd_pic_create(&d, &o) == PSATD_EUNSUPPORTED && o == NULL);
     d.dt = 0.5;
+    d.shape = 4; /* no B-spline of degree 4 */
+    CHECK(psatd_pic_create(&d, &o) == PSATD_EINVAL && o == NULL);
+    d.shape = 2;
     d.tile = 0;
     CHECK(psatd_pic_create(&d, &o) == PSATD_EINVAL);
     psatd_pic_destroy(NULL);

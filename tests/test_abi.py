@@ -210,7 +210,7 @@ def test_tune_cache_reader_rejects_stale_and_corrupt_entries(lib, tmp_path):
 
 def _pic_desc(lib, **kw):
     d = dict(gx=16, gy=16, gz=16, dx=1.0, dy=1.0, dz=1.0, dt=0.5, c=1.0, q=1.0, q_over_m=1.0, max_particles=100,
-             tile=8, precision=0, flags=0)
+             tile=8, precision=0, flags=0, shape=0)
     d.update(kw)
     return lib.PicDesc(**d)
 
@@ -218,7 +218,8 @@ def _pic_desc(lib, **kw):
 @pytest.mark.parametrize("bad,code", [(dict(gx=0), "EINVAL"), (dict(dz=0.0), "EINVAL"), (dict(dt=-0.5), "EINVAL"),
                                       (dict(c=0.0), "EINVAL"), (dict(precision=3), "EINVAL"),
                                       (dict(flags=2), "EINVAL"), (dict(tile=0), "EINVAL"), (dict(tile=17), "EINVAL"),
-                                      (dict(max_particles=-1), "EINVAL"), (dict(dt=1.5), "EUNSUPPORTED"),
+                                      (dict(max_particles=-1), "EINVAL"), (dict(shape=4), "EINVAL"),
+                                      (dict(shape=-1), "EINVAL"), (dict(dt=1.5), "EUNSUPPORTED"),
                                       (dict(dy=0.4), "EUNSUPPORTED")])
 def test_pic_descriptors_are_checked_on_the_host(lib, bad, code):
     h = ctypes.c_void_p()

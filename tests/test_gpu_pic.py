@@ -1,19 +1,20 @@
 """GPU parity of the particle side of the PIC cycle (psatd_pic_*) against the oracle.
 
 The oracle (oracle/pic.py) is pinned in tests/test_oracle_pic.py by the tent
-function, exact charge conservation, gather/deposit adjointness, exact linear
-interpolation and Boris closed forms.  Here the HIP kernels are compared with it
-element by element on seeded warm-plasma particles (edge cases included: nodes,
-the periodic edge, tile corners) on collocated and staggered grids, with D1 tiles
-that divide the grid and tiles that leave a ragged tail, a grid smaller than one
-tile, an empty particle set, and a full PIC cycle (push, deposit, Maxwell step on
-the FFT boxes) against the oracle's cycle.
+function, the truncated-power form of the B-splines, their moments, exact charge
+conservation, gather/deposit adjointness, exact linear interpolation and Boris
+closed forms.  Here the HIP kernels are compared with it element by element on
+seeded warm-plasma particles (edge cases included: nodes, the periodic edge, tile
+corners) on collocated and staggered grids, for particle shapes of degree 1, 2
+and 3, with D1 tiles that divide the grid and tiles that leave a ragged tail, a
+grid smaller than one tile, an empty particle set, and a full PIC cycle (push,
+deposit, Maxwell step on the FFT boxes) against the oracle's cycle.
 
 Tolerances.  FP64: 1e-12 relative (max norm); the deposit's atomic sums change
 only the order of rounding.  FP32: positions and momenta to 2e-6 of their scale
-(a few ulps of the gather of eight terms and the Boris step), grid sums to 2e-5
-of the largest cell value (fp32 positions set the weights to ~1e-6 absolute and a
-cell sums up to a few hundred weighted terms).
+(a few ulps of the gather of up to 64 terms and the Boris step), grid sums to
+2e-5 of the largest cell value (fp32 positions set the weights to ~1e-6 absolute
+and a cell sums up to a few hundred weighted terms).
 """
 
 import numpy as np
@@ -58,7 +59,8 @@ def _g1_fields(seed, gdims, scale=0.3):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("staggered", [False, True])
-def test_push_matches_oracle(lib, precision, staggered):
+@pytest.mark.parametrize("shape", [1, 2, 3])
+def test_push_matches_oracle(lib, precision, staggered, shape):
     import torch
 
     L = _lengths(G1, D)
@@ -66,9 +68,9 @@ def test_push_matches_oracle(lib, precision, staggered):
     x, u = _as_inputs(x, u, precision, L)
     g1 = _g1_fields(161, G1)
     qm = -1.3
-    xr, ur = pic.push(x, u, g1, g1.shape[1:], D, qm, DT, C, staggered=staggered)
+    xr, ur = pic.push(x, u, g1, g1.shape[1:], D, qm, DT, C, staggered=staggered, order=shape)
     p = lib.Pic(G1, dx=D, dt=DT, c=C, q=1.0, q_over_m=qm, max_particles=len(x), tile=8, precision=precision,
-                staggered=staggered)
+                staggered=staggered, shape=shape)
     g = _gpu(g1, p)
     xg, ug = _gpu(x.T, p), _gpu(u.T, p)
     xo = torch.empty_like(xg)
@@ -83,7 +85,7 @@ def test_push_matches_oracle(lib, precision, staggered):
     p.close()
 
 
-def _deposit_case(lib, precision, staggered, gdims, tile, n, seed):
+def _deposit_case(lib, precision, staggered, gdims, tile, n, seed, shape=1):
     import torch
 
     L = _lengths(gdims, D)
@@ -95,10 +97,10 @@ def _deposit_case(lib, precision, staggered, gdims, tile, n, seed):
     x1, _ = _as_inputs(x1, u, precision, L)
     gshape = (gdims[2], gdims[1], gdims[0])
     q = -0.37
-    J, r0, r1 = pic.sources(x0, x1, u, q, gshape, D, DT, C, staggered=staggered)
+    J, r0, r1 = pic.sources(x0, x1, u, q, gshape, D, DT, C, staggered=staggered, order=shape)
     ref = np.concatenate([J, r0[None], r1[None]])
     p = lib.Pic(gdims, dx=D, dt=DT, c=C, q=q, q_over_m=1.0, max_particles=max(n, 1), tile=tile, precision=precision,
-                staggered=staggered)
+                staggered=staggered, shape=shape)
     g1 = _g1_fields(seed + 1, gdims)
     g = _gpu(g1, p)
     p.deposit(g, _gpu(x0.T, p), _gpu(x1.T, p), _gpu(u.T, p))
@@ -111,8 +113,9 @@ def _deposit_case(lib, precision, staggered, gdims, tile, n, seed):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("staggered", [False, True])
 @pytest.mark.parametrize("tile", [8, 5])
-def test_deposit_matches_oracle(lib, precision, staggered, tile):
-    got, g1, ref = _deposit_case(lib, precision, staggered, G1, tile, 20000, 162)
+@pytest.mark.parametrize("shape", [1, 2, 3])
+def test_deposit_matches_oracle(lib, precision, staggered, tile, shape):
+    got, g1, ref = _deposit_case(lib, precision, staggered, G1, tile, 20000, 162, shape)
     assert np.array_equal(got[0:6], g1[0:6].astype(np.float32 if precision == "fp32" else np.float64))
     tol = 1e-12 if precision == "fp64" else 2e-5
     err = np.abs(got[6:] - ref).max() / np.abs(ref).max()
@@ -124,8 +127,11 @@ def test_deposit_matches_oracle(lib, precision, staggered, tile):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_deposit_on_a_grid_smaller_than_a_tile(lib, precision):
-    got, _, ref = _deposit_case(lib, precision, True, (6, 5, 3), 8, 700, 163)
+@pytest.mark.parametrize("shape", [1, 3])
+def test_deposit_on_a_grid_smaller_than_a_tile(lib, precision, shape):
+    # with shape 3 the 4-point stencil covers more than the 3 cells along z: the
+    # periodic images of one point add up
+    got, _, ref = _deposit_case(lib, precision, True, (6, 5, 3), 8, 700, 163, shape)
     tol = 1e-12 if precision == "fp64" else 2e-5
     assert np.abs(got[6:] - ref).max() / np.abs(ref).max() <= tol
 
@@ -149,11 +155,11 @@ def test_deposit_of_no_particles_clears_the_sources(lib):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("staggered", [False, True])
-def test_pic_cycle_matches_oracle(lib, precision, staggered):
+@pytest.mark.parametrize("staggered,shape", [(False, 1), (True, 1), (False, 2), (True, 3)])
+def test_pic_cycle_matches_oracle(lib, precision, staggered, shape):
     """Three PIC cycles: gather + push, deposit, local PSATD step on four FFT boxes (D2)
     whose edges differ from the D1 tiles, against the same cycle in the oracle; on the
-    collocated and on the staggered (Yee) grid."""
+    collocated and on the staggered (Yee) grid, with linear and higher-order shapes."""
     import torch
 
     gdims, d, dt, c = (32, 24, 20), (1.0, 1.0, 1.0), 0.45, 1.0
@@ -169,7 +175,7 @@ def test_pic_cycle_matches_oracle(lib, precision, staggered):
     f = 0.05 * synth.random_fields(synth.rng_for(166, 0), gshape, 11, 1.0)
     f[6:] = 0.0
     p = lib.Pic(gdims, dx=d, dt=dt, c=c, q=q, q_over_m=qm, max_particles=len(x), tile=8, precision=precision,
-                staggered=staggered)
+                staggered=staggered, shape=shape)
     batch = lib.Batch(boxes, gdims, dx=d, dt=dt, precision=precision)
     g = _gpu(f, p)
     f = g.double().cpu().numpy()
@@ -179,8 +185,8 @@ def test_pic_cycle_matches_oracle(lib, precision, staggered):
         p.push(g, xg, ug, xo)
         p.deposit(g, xo, xg, ug)
         batch.step(g)
-        xn, u = pic.push(x, u, f, gshape, d, qm, dt, c, staggered=staggered)
-        J, r0, r1 = pic.sources(x, xn, u, q, gshape, d, dt, c, staggered=staggered)
+        xn, u = pic.push(x, u, f, gshape, d, qm, dt, c, staggered=staggered, order=shape)
+        J, r0, r1 = pic.sources(x, xn, u, q, gshape, d, dt, c, staggered=staggered, order=shape)
         f[6:9], f[9], f[10] = J, r0, r1
         f = domain.local_step(f, boxes, d, dt, c)
         x = xn
@@ -194,8 +200,8 @@ def test_pic_cycle_matches_oracle(lib, precision, staggered):
     p.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_deposit_at_scale_sampled_cells(lib, precision):
+@pytest.mark.parametrize("precision,shape", [("fp32", 1), ("fp64", 1), ("fp32", 3)])
+def test_deposit_at_scale_sampled_cells(lib, precision, shape):
     """256 x 128 x 128 cells, 8 particles per cell (33.5 M): total charge exact to rounding,
     and 48 sampled cells of every slot against the oracle's deposit of the particles
     whose stencil reaches them."""
@@ -205,7 +211,7 @@ def test_deposit_at_scale_sampled_cells(lib, precision):
     gshape = (gdims[2], gdims[1], gdims[0])
     d, dt, c, q = (1.0, 1.0, 1.0), 0.5, 1.0, 0.01
     n = 8 * gdims[0] * gdims[1] * gdims[2]
-    p = lib.Pic(gdims, dx=d, dt=dt, c=c, q=q, max_particles=n, tile=8, precision=precision)
+    p = lib.Pic(gdims, dx=d, dt=dt, c=c, q=q, max_particles=n, tile=8, precision=precision, shape=shape)
     gen = torch.Generator(device="cuda").manual_seed(167)
     L = torch.tensor(_lengths(gdims, d), dtype=p.dtype, device="cuda")[:, None]
     x0 = torch.rand((3, n), generator=gen, dtype=p.dtype, device="cuda") * L
@@ -231,12 +237,13 @@ def test_deposit_at_scale_sampled_cells(lib, precision):
         dist0 = torch.remainder(x0 - ctr + 0.5 * L, L) - 0.5 * L
         dist1 = torch.remainder(x1 - ctr + 0.5 * L, L) - 0.5 * L
         # every particle whose stencil can reach the cell: start (rho_old, and the mid-point
-        # of J within half a cell of it) or end (rho_new) within 2.5 cells
+        # of J within a quarter cell of it) or end (rho_new) within 2.5 cells (the cubic
+        # stencil reaches 2 cells)
         m = (dist0.abs() <= 2.5).all(0) | (dist1.abs() <= 2.5).all(0)
         sub = m if sub is None else sub | m
     idx = torch.nonzero(sub).squeeze(1)
     xs0, xs1, us = (t[:, idx].double().cpu().numpy().T for t in (x0, x1, u))
-    J, r0, r1 = pic.sources(xs0, xs1, us, q, gshape, d, dt, c)
+    J, r0, r1 = pic.sources(xs0, xs1, us, q, gshape, d, dt, c, order=shape)
     ref = np.concatenate([J, r0[None], r1[None]])
     got = g[6:].double().cpu().numpy()
     scale = np.abs(got).max()
