@@ -128,17 +128,41 @@ __device__ __forceinline__ void grid_points(Points<K, T>& g, const PicArgs<T>& a
   }
 }
 
+// K + 1 consecutive values of a row, read with one multi-word load (4-byte aligned vectors)
+template <int K, typename T>
+struct RowRun {
+  T v[K + 1];
+};
+template <int K, typename T>
+__device__ __forceinline__ RowRun<K, T> load_run(const T* p) {
+  typedef T vec_t __attribute__((ext_vector_type(K + 1), aligned(alignof(T))));
+  const vec_t x = *reinterpret_cast<const vec_t*>(p);
+  RowRun<K, T> r;
+#pragma unroll
+  for (int c = 0; c <= K; ++c) r.v[c] = x[c];
+  return r;
+}
+
 template <int K, typename T>
 __device__ __forceinline__ T gather_at(const T* __restrict__ f, const Points<K, T>& g) {
   T acc = 0;
+  // the x points are consecutive unless the stencil wraps around the periodic edge
+  const bool run = g.xs[K] == g.xs[0] + K;
 #pragma unroll
   for (int cz = 0; cz <= K; ++cz)
 #pragma unroll
     for (int cy = 0; cy <= K; ++cy) {
       const T wyz = g.wy[cy] * g.wz[cz];
-      const int row = g.zs[cz] + g.ys[cy];
+      const T* row = f + g.zs[cz] + g.ys[cy];
+      RowRun<K, T> r;
+      if (run) {
+        r = load_run<K>(row + g.xs[0]);
+      } else {
 #pragma unroll
-      for (int cx = 0; cx <= K; ++cx) acc += f[row + g.xs[cx]] * (g.wx[cx] * wyz);
+        for (int cx = 0; cx <= K; ++cx) r.v[cx] = row[g.xs[cx]];
+      }
+#pragma unroll
+      for (int cx = 0; cx <= K; ++cx) acc += r.v[cx] * (g.wx[cx] * wyz);
     }
   return acc;
 }
@@ -161,7 +185,30 @@ __global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs
   const T x = p.x[0][i], y = p.x[1][i], z = p.x[2][i];
   T E[3], B[3];
   Points<K, T> g;
-  if constexpr (STAG) {
+  if constexpr (K > 1) {
+    // one field at a time (a loop that is not unrolled), so that the (K+1)^3 loads of one
+    // field are in flight together without the registers of all six
+    T eb[6];
+    if constexpr (!STAG) grid_points<K>(g, a, x, y, z, 0, 0, 0);
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {
+      if constexpr (STAG) {
+        // E_a half a cell up along a; B_a along the two other axes
+        const int c = k < 3 ? k : k - 3;
+        const bool e = k < 3;
+        grid_points<K>(g, a, x, y, z, (c == 0) == e, (c == 1) == e, (c == 2) == e);
+      }
+      const T v = gather_at<K>(p.f[k], g);
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (j == k) eb[j] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      E[c] = eb[c];
+      B[c] = eb[3 + c];
+    }
+  } else if constexpr (STAG) {
     // E_a half a cell up along a; B_a along the two other axes
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
