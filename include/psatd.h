@@ -416,7 +416,10 @@ typedef struct {
 typedef struct psatd_pic psatd_pic;
 
 /* Checks the descriptor and allocates the per-tile lists (12 bytes per tile
- * + 4 bytes per particle).  A tile accumulates over itself and guard cells per
+ * + 4 bytes per particle); for shapes 2 and 3 on grids that the tiles divide
+ * with at least two tiles per axis, also one block of 5 (tile + 5)^3 values
+ * per tile (52 bytes per cell in FP32 at tile 8; without that memory the
+ * deposit falls back to atomics).  A tile accumulates over itself and guard cells per
  * axis, one below and two above for shape 1, two below and three above for
  * shapes 2 and 3: the reach of the stencil of a particle that started in the
  * tile and moved less than a cell (tile 8: 11^3 or 13^3 cells, 53 or 88 KB of
@@ -444,9 +447,12 @@ int psatd_pic_push(psatd_pic* pic, void* const* g1, void* const* x, void* const*
  * particles are listed per D1 tile of their start position, each tile
  * accumulates in LDS over itself and its guard cells in 64-bit fixed point (a
  * power-of-two scale per tile: exact integer sums of the rounded
- * contributions, independent of order), and the block is added into G1 with
- * floating-point atomics, whose order between neighbouring tiles varies from
- * run to run. */
+ * contributions), and the block is added into G1 with floating-point atomics,
+ * whose order between neighbouring tiles varies from run to run; with the
+ * per-tile blocks of shapes 2 and 3 (see psatd_pic_create) the blocks are
+ * stored and each G1 cell sums the blocks that cover it in a fixed order.
+ * A tile's particle list is built with atomics, so the rounding of the
+ * per-thread sums may still vary in the last bits. */
 int psatd_pic_deposit(psatd_pic* pic, void* const* g1, const void* const* x_old, const void* const* x,
                       const void* const* u, int n, void* stream);
 

@@ -454,9 +454,11 @@ __device__ __forceinline__ void stencil_run(fixed_t* blk, int E, Stencil<T>& acc
 }
 
 // One workgroup per D1 tile: its particles' J (mid-point), rho_old (start) and rho_new
-// (end) into LDS over the tile and its guard cells, then the block added into G1.
+// (end) into LDS over the tile and its guard cells, then the block either added into G1
+// with global atomics (blocks == nullptr) or stored whole, tile by tile, into `blocks`
+// ([tile][quantity][z][y][x], E^3 values per quantity) for k_gather_blocks.
 template <typename T, int K>
-__global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, DepPtrs<T> p) {
+__global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, DepPtrs<T> p, T* __restrict__ blocks) {
   extern __shared__ double2 pic_smem[];
   fixed_t* lds = reinterpret_cast<fixed_t*>(pic_smem);
   constexpr int GL = Reach<K>::lo;
@@ -531,9 +533,17 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
         if (acc[q].l0 >= 0) stencil_add(lds + q * ncl, E, acc[q], q < 3 ? sj : sr);
     }
     __syncthreads();
-    // the block (tile and guards) added into G1: guard cells are the neighbours' cells.
-    // Rows (f, z, y) are walked with carries, so no element needs a division.
-    if (r0 < R) {
+    if (blocks) {
+      // the whole block, unscaled, in the tile's slot (consecutive threads, consecutive words)
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        const double sc = ldexp(1.0, -(f < 3 ? ejc : erc));
+        T* dst = blocks + ((long long)t * 5 + f) * ncl;
+        for (int i = tid; i < ncl; i += blockDim.x) dst[i] = (T)((double)(long long)lds[f * ncl + i] * sc);
+      }
+    } else if (r0 < R) {
+      // the block (tile and guards) added into G1: guard cells are the neighbours' cells.
+      // Rows (f, z, y) are walked with carries, so no element needs a division.
       auto wrap_near = [](int v, int n) {  // v in [-n, ...): one add or subtract except on tiny grids
         if (v < 0) v += n;
         if (v >= n) {
@@ -568,6 +578,57 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
   }
 }
 
+// The blocks stored by k_deposit_tiles summed into G1, one thread per cell: a cell lies in
+// the block of its own tile and, near a tile face, in the block of the neighbour across
+// it.  Requires tiles that divide the grid, at least two tiles per axis and guards no wider
+// than a tile, so that along each axis only the tiles t - 1, t, t + 1 reach a cell, each
+// once.  Every cell is written (no zeroing first), with a fixed order of the sums.
+template <typename T, int K>
+__global__ void __launch_bounds__(256) k_gather_blocks(PicArgs<T> a, DepPtrs<T> p, const T* __restrict__ blocks) {
+  constexpr int GL = Reach<K>::lo;
+  const int T_ = a.tile, E = T_ + GL + Reach<K>::hi;
+  const long long ncl = (long long)E * E * E;
+  const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ncell = (long long)a.gx * a.gy * a.gz;
+  if (cell >= ncell) return;
+  const int x = (int)(cell % a.gx), y = (int)((cell / a.gx) % a.gy), z = (int)(cell / ((long long)a.gx * a.gy));
+  // per axis: the tiles whose block covers the cell, and the cell's index in that block
+  auto reach = [&](int c, int n, int nt, int* ts, int* ls) {
+    const int own = c / T_;
+    int m = 0;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+      int t = own + d;
+      if (t < 0) t += nt;
+      if (t >= nt) t -= nt;
+      if ((m > 0 && ts[0] == t) || (m > 1 && ts[1] == t)) continue;
+      int l = c - t * T_ + GL;
+      if (l < 0) l += n;
+      if (l >= n) l -= n;
+      if (l < E) {
+        ts[m] = t;
+        ls[m] = l;
+        ++m;
+      }
+    }
+    return m;
+  };
+  int tsx[3], lsx[3], tsy[3], lsy[3], tsz[3], lsz[3];
+  const int mx = reach(x, a.gx, a.tx, tsx, lsx), my = reach(y, a.gy, a.ty, tsy, lsy),
+            mz = reach(z, a.gz, a.tz, tsz, lsz);
+  T acc[5] = {0, 0, 0, 0, 0};
+  for (int iz = 0; iz < mz; ++iz)
+    for (int iy = 0; iy < my; ++iy)
+      for (int ix = 0; ix < mx; ++ix) {
+        const long long t = ((long long)tsz[iz] * a.ty + tsy[iy]) * a.tx + tsx[ix];
+        const T* b = blocks + t * 5 * ncl + ((long long)lsz[iz] * E + lsy[iy]) * E + lsx[ix];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) acc[f] += b[f * ncl];
+      }
+#pragma unroll
+  for (int f = 0; f < 5; ++f) p.g[f][cell] = acc[f];
+}
+
 }  // namespace
 }  // namespace psatd
 
@@ -581,6 +642,7 @@ struct psatd_pic {
   int* offset = nullptr;
   int* cursor = nullptr;
   int* list = nullptr;
+  void* blocks = nullptr;  // per-tile deposit blocks (NULL: blocks merged with atomics)
 };
 
 namespace {
@@ -653,13 +715,18 @@ int pic_push(psatd_pic* o, void* const* g1, void* const* x, void* const* u, void
 }
 
 template <typename T, int K>
-void launch_deposit(const PicArgs<T>& a, const DepPtrs<T>& p, int ntiles, size_t lds, hipStream_t s) {
+void launch_deposit(const PicArgs<T>& a, const DepPtrs<T>& p, T* blocks, size_t lds, hipStream_t s) {
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_deposit_tiles<T, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
   // one tile per workgroup (the loop inside covers grids beyond the cap)
-  const unsigned grid = (unsigned)std::min(ntiles, 1 << 20);
-  hipLaunchKernelGGL((k_deposit_tiles<T, K>), dim3(grid), dim3(kPicThreads), lds, s, a, p);
+  const unsigned grid = (unsigned)std::min(a.ntiles, 1 << 20);
+  hipLaunchKernelGGL((k_deposit_tiles<T, K>), dim3(grid), dim3(kPicThreads), lds, s, a, p, blocks);
+  if (blocks) {
+    const long long ncell = (long long)a.gx * a.gy * a.gz;
+    hipLaunchKernelGGL((k_gather_blocks<T, K>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s, a, p,
+                       (const T*)blocks);
+  }
 }
 
 template <typename T>
@@ -678,7 +745,10 @@ int pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const v
   p.list = o->list;
   const PicArgs<T> a = pic_args<T>(o, n);
   const long long ncell = (long long)o->d.gx * o->d.gy * o->d.gz;
-  hipLaunchKernelGGL(k_zero_fields<T>, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, p, ncell);
+  T* blocks = (T*)o->blocks;
+  // with per-tile blocks every cell is written by the gather; otherwise the atomics add
+  // into zeroed arrays
+  if (!blocks || n == 0) hipLaunchKernelGGL(k_zero_fields<T>, dim3(blocks_for(ncell, 256)), dim3(256), 0, s, p, ncell);
   if (n == 0) return PSATD_OK;
   hipLaunchKernelGGL(k_zero_int, dim3(blocks_for(o->ntiles, 256)), dim3(256), 0, s, o->count, o->ntiles);
   hipLaunchKernelGGL(k_tile_count<T>, dim3(blocks_for(n, kPicThreads)), dim3(kPicThreads), 0, s, a, p);
@@ -687,11 +757,11 @@ int pic_deposit(psatd_pic* o, void* const* g1, const void* const* x_old, const v
   const int shape = shape_of(o->d);
   const size_t lds = pic_lds_bytes(o->d.tile, shape);
   if (shape == 1)
-    launch_deposit<T, 1>(a, p, o->ntiles, lds, s);
+    launch_deposit<T, 1>(a, p, blocks, lds, s);
   else if (shape == 2)
-    launch_deposit<T, 2>(a, p, o->ntiles, lds, s);
+    launch_deposit<T, 2>(a, p, blocks, lds, s);
   else
-    launch_deposit<T, 3>(a, p, o->ntiles, lds, s);
+    launch_deposit<T, 3>(a, p, blocks, lds, s);
   return PSATD_OK;
 }
 
@@ -747,6 +817,25 @@ int psatd_pic_create(const psatd_pic_desc* d, psatd_pic** out) {
       delete o;
       return report_error(PSATD_ENOMEM, "particle workspace allocation failed");
     }
+  // Per-tile blocks for the atomic-free merge (see k_gather_blocks) for shapes of degree 2
+  // and 3, where the tiling allows it: their blocks hold 13^3 cells per 8^3 tile, and
+  // storing and gathering them beats adding them with global atomics.  For degree 1 (11^3
+  // cells per 8^3 tile) the atomics are faster.  Without the memory the blocks are merged
+  // with atomics.
+  {
+    const int shape = shape_of(*d), T = d->tile;
+    const int reach = Reach<2>::lo + Reach<2>::hi;
+    const bool tiled = shape >= 2 && d->gx % T == 0 && d->gy % T == 0 && d->gz % T == 0 && o->tx >= 2 &&
+                       o->ty >= 2 && o->tz >= 2 && reach <= T;
+    if (tiled) {
+      const size_t e = (size_t)T + reach;
+      const size_t b = (size_t)o->ntiles * 5 * e * e * e * (o->fp64 ? sizeof(double) : sizeof(float));
+      if (hipMalloc(&o->blocks, b) != hipSuccess) {
+        (void)hipGetLastError();
+        o->blocks = nullptr;
+      }
+    }
+  }
   *out = o;
   return PSATD_OK;
 }
@@ -755,6 +844,7 @@ void psatd_pic_destroy(psatd_pic* o) {
   if (!o) return;
   for (int* q : {o->count, o->offset, o->cursor, o->list})
     if (q) (void)hipFree(q);
+  if (o->blocks) (void)hipFree(o->blocks);
   delete o;
 }
 
