@@ -182,7 +182,10 @@ template <typename T, bool STAG, int K>
 __global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs<T> p) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const T x = p.x[0][i], y = p.x[1][i], z = p.x[2][i];
+  // the particle arrays stream through once (non-temporal), which leaves the caches to the
+  // field rows that neighbouring particles gather again
+  const T x = __builtin_nontemporal_load(&p.x[0][i]), y = __builtin_nontemporal_load(&p.x[1][i]),
+          z = __builtin_nontemporal_load(&p.x[2][i]);
   T E[3], B[3];
   Points<K, T> g;
   if constexpr (K > 1) {
@@ -227,7 +230,8 @@ __global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs
   }
   const T h = T(0.5) * a.qm * a.dt;
   const T ic2 = T(1) / (a.c * a.c);
-  T um[3] = {p.u[0][i] + h * E[0], p.u[1][i] + h * E[1], p.u[2][i] + h * E[2]};
+  T um[3] = {__builtin_nontemporal_load(&p.u[0][i]) + h * E[0], __builtin_nontemporal_load(&p.u[1][i]) + h * E[1],
+             __builtin_nontemporal_load(&p.u[2][i]) + h * E[2]};
   const T gm = sqrt(T(1) + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]) * ic2);
   const T t[3] = {h * B[0] / gm, h * B[1] / gm, h * B[2] / gm};
   const T t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
@@ -244,9 +248,9 @@ __global__ void __launch_bounds__(kPicThreads) k_pic_push(PicArgs<T> a, PushPtrs
     T xn = xs[k] + a.dt * un[k] / gn;
     xn -= L[k] * floor(xn / L[k]);
     if (xn >= L[k]) xn -= L[k];  // rounding at the upper edge
-    p.x_old[k][i] = xs[k];
-    p.x[k][i] = xn;
-    p.u[k][i] = un[k];
+    __builtin_nontemporal_store(xs[k], &p.x_old[k][i]);
+    __builtin_nontemporal_store(xn, &p.x[k][i]);
+    __builtin_nontemporal_store(un[k], &p.u[k][i]);
   }
 }
 
