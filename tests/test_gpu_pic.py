@@ -172,11 +172,13 @@ def test_deposit_on_a_grid_smaller_than_a_tile(lib, precision, shape):
     assert np.abs(got[6:] - ref).max() / np.abs(ref).max() <= tol
 
 
-def test_deposit_of_no_particles_clears_the_sources(lib):
+@pytest.mark.parametrize("shape,gdims,tile", [(1, G1, 8), (2, (40, 20, 30), 5)])
+def test_deposit_of_no_particles_clears_the_sources(lib, shape, gdims, tile):
+    # (degree 2 on a grid the tiles divide: the path with per-tile blocks)
     import torch
 
-    p = lib.Pic(G1, dx=D, dt=DT, c=C, max_particles=10, precision="fp64")
-    g1 = _g1_fields(164, G1)
+    p = lib.Pic(gdims, dx=D, dt=DT, c=C, max_particles=10, tile=tile, precision="fp64", shape=shape)
+    g1 = _g1_fields(164, gdims)
     g = _gpu(g1, p)
     e = torch.empty((3, 0), dtype=torch.float64, device="cuda")
     p.deposit(g, e, e, e)
