@@ -339,7 +339,7 @@ long long psatd_device_bytes_in_use(void);
 
 /* Reads an autotuner cache file (the format psatd_plan_autotune writes) into
  * the process cache without a GPU.  An entry is accepted only if the file's
- * schema version is this build's and its radices are compiled and multiply to
+ * schema version is the library's own and its radices are compiled and multiply to
  * the transform length named in its key; tiles are checked again against the
  * plan's limits when an entry is used.  Reading stops at malformed text.
  * *accepted / *rejected (either may be NULL) receive the counts.  A missing
