@@ -255,7 +255,6 @@ struct dft {
       }
     } else {
       // R = P * Q; input n = Q n1 + n2, output k = k1 + P k2.
-      constexpr int Q = R / P;
       cx<T> y[R];
       split_stage<0>(x, y);
       // y[n2 * P + k1] now holds the twiddled P-point results; Q-point DFTs over n2.
