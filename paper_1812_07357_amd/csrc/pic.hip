@@ -582,55 +582,56 @@ __global__ void __launch_bounds__(kPicThreads) k_deposit_tiles(PicArgs<T> a, Dep
   }
 }
 
-// The blocks stored by k_deposit_tiles summed into G1, one thread per cell: a cell lies in
-// the block of its own tile and, near a tile face, in the block of the neighbour across
+// The blocks stored by k_deposit_tiles summed into G1: one workgroup per tile, one thread
+// per cell of the tile (x fastest), so that a wave reads rows of several block rows at once.
+// A cell lies in the block of its own tile and, within Reach<K>::hi cells of the tile's
+// lower face or Reach<K>::lo cells of its upper face, in the block of the neighbour across
 // it.  Requires tiles that divide the grid, at least two tiles per axis and guards no wider
-// than a tile, so that along each axis only the tiles t - 1, t, t + 1 reach a cell, each
-// once.  Every cell is written (no zeroing first), with a fixed order of the sums.
+// than a tile, so that along each axis a cell is reached by its own tile and at most one
+// neighbour (with two tiles per axis both neighbours are the same tile, reached through one
+// face or the other).  Every cell is written (no zeroing first), with a fixed order of the
+// sums.
 template <typename T, int K>
 __global__ void __launch_bounds__(256) k_gather_blocks(PicArgs<T> a, DepPtrs<T> p, const T* __restrict__ blocks) {
-  constexpr int GL = Reach<K>::lo;
-  const int T_ = a.tile, E = T_ + GL + Reach<K>::hi;
+  constexpr int GL = Reach<K>::lo, GH = Reach<K>::hi;
+  const int T_ = a.tile, E = T_ + GL + GH, T2 = T_ * T_;
   const long long ncl = (long long)E * E * E;
-  const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long ncell = (long long)a.gx * a.gy * a.gz;
-  if (cell >= ncell) return;
-  const int x = (int)(cell % a.gx), y = (int)((cell / a.gx) % a.gy), z = (int)(cell / ((long long)a.gx * a.gy));
-  // per axis: the tiles whose block covers the cell, and the cell's index in that block
-  auto reach = [&](int c, int n, int nt, int* ts, int* ls) {
-    const int own = c / T_;
-    int m = 0;
-#pragma unroll
-    for (int d = -1; d <= 1; ++d) {
-      int t = own + d;
-      if (t < 0) t += nt;
-      if (t >= nt) t -= nt;
-      if ((m > 0 && ts[0] == t) || (m > 1 && ts[1] == t)) continue;
-      int l = c - t * T_ + GL;
-      if (l < 0) l += n;
-      if (l >= n) l -= n;
-      if (l < E) {
-        ts[m] = t;
-        ls[m] = l;
-        ++m;
-      }
+  const int tile = blockIdx.x;
+  const int tz = tile / (a.tx * a.ty), ty = (tile - tz * a.tx * a.ty) / a.tx, tx = tile - (tz * a.ty + ty) * a.tx;
+  // per axis: the tiles whose block covers local cell c, and the cell's index in each
+  auto reach = [&](int c, int t, int nt, int* ts, int* ls) {
+    ts[0] = t;
+    ls[0] = c + GL;
+    int m = 1;
+    if (c < GH) {  // in the upper guard of the tile below
+      ts[m] = t == 0 ? nt - 1 : t - 1;
+      ls[m] = c + T_ + GL;
+      ++m;
+    } else if (c >= T_ - GL) {  // in the lower guard of the tile above
+      ts[m] = t == nt - 1 ? 0 : t + 1;
+      ls[m] = c - T_ + GL;
+      ++m;
     }
     return m;
   };
-  int tsx[3], lsx[3], tsy[3], lsy[3], tsz[3], lsz[3];
-  const int mx = reach(x, a.gx, a.tx, tsx, lsx), my = reach(y, a.gy, a.ty, tsy, lsy),
-            mz = reach(z, a.gz, a.tz, tsz, lsz);
-  T acc[5] = {0, 0, 0, 0, 0};
-  for (int iz = 0; iz < mz; ++iz)
-    for (int iy = 0; iy < my; ++iy)
-      for (int ix = 0; ix < mx; ++ix) {
-        const long long t = ((long long)tsz[iz] * a.ty + tsy[iy]) * a.tx + tsx[ix];
-        const T* b = blocks + t * 5 * ncl + ((long long)lsz[iz] * E + lsy[iy]) * E + lsx[ix];
+  for (int q = threadIdx.x; q < T2 * T_; q += blockDim.x) {
+    const int lz = q / T2, ly = (q - lz * T2) / T_, lx = q - lz * T2 - ly * T_;
+    int tsx[2], lsx[2], tsy[2], lsy[2], tsz[2], lsz[2];
+    const int mx = reach(lx, tx, a.tx, tsx, lsx), my = reach(ly, ty, a.ty, tsy, lsy),
+              mz = reach(lz, tz, a.tz, tsz, lsz);
+    T acc[5] = {0, 0, 0, 0, 0};
+    for (int iz = 0; iz < mz; ++iz)
+      for (int iy = 0; iy < my; ++iy)
+        for (int ix = 0; ix < mx; ++ix) {
+          const long long t = ((long long)tsz[iz] * a.ty + tsy[iy]) * a.tx + tsx[ix];
+          const T* b = blocks + t * 5 * ncl + ((long long)lsz[iz] * E + lsy[iy]) * E + lsx[ix];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) acc[f] += b[f * ncl];
-      }
+          for (int f = 0; f < 5; ++f) acc[f] += b[f * ncl];
+        }
+    const long long cell = ((long long)(tz * T_ + lz) * a.gy + (ty * T_ + ly)) * a.gx + (tx * T_ + lx);
 #pragma unroll
-  for (int f = 0; f < 5; ++f) p.g[f][cell] = acc[f];
+    for (int f = 0; f < 5; ++f) p.g[f][cell] = acc[f];
+  }
 }
 
 }  // namespace
@@ -726,11 +727,7 @@ void launch_deposit(const PicArgs<T>& a, const DepPtrs<T>& p, T* blocks, size_t 
   // one tile per workgroup (the loop inside covers grids beyond the cap)
   const unsigned grid = (unsigned)std::min(a.ntiles, 1 << 20);
   hipLaunchKernelGGL((k_deposit_tiles<T, K>), dim3(grid), dim3(kPicThreads), lds, s, a, p, blocks);
-  if (blocks) {
-    const long long ncell = (long long)a.gx * a.gy * a.gz;
-    hipLaunchKernelGGL((k_gather_blocks<T, K>), dim3(blocks_for(ncell, 256)), dim3(256), 0, s, a, p,
-                       (const T*)blocks);
-  }
+  if (blocks) hipLaunchKernelGGL((k_gather_blocks<T, K>), dim3(a.ntiles), dim3(256), 0, s, a, p, (const T*)blocks);
 }
 
 template <typename T>
